@@ -1,0 +1,599 @@
+/*
+ * sco_oracle.c -- plain, serial, FP64 CPU oracle of one stochastic-cutoff (SCO) step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls this
+ * file: only tests/, the smoke check and the CPU-baseline leg of bench.py use it.  It
+ * shares no code, header, table or constant generator with the HIP library.
+ *
+ * What it computes (paper: "Parallelized Stochastic Cutoff Method for Long-Range
+ * Interacting Systems", Endo, Toga & Sasaki):
+ *   - the model: Ising spins s_i = +-1 perpendicular to a 2-D square lattice, i.e.
+ *     Eq. (6) with every spin along z so that the (S.r)(S.r) term vanishes:
+ *         H = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j,  J_ij = D / r_ij^3
+ *     (open lattice), or J_ij summed over the periodic images |n_x|,|n_y| <= n_images;
+ *   - step (A) / Fig. 1 step (1): stochastic potential switching of every dipolar
+ *     bond, Eqs. (1)-(3), with V^max = kappa * J_ij (kappa >= 1);
+ *   - Fig. 1 step (2): vertex colouring of the surviving-bond graph (united with the
+ *     never-switched nearest-neighbour exchange bonds) by Kuhn-Wattenhofer colour
+ *     reduction, each level run as basic colour reduction with the locally-maximal
+ *     rule (2)' of Sec. 2.3.2, in synchronous (Jacobi) rounds, Sec. 2.3.1 / 2.3.3;
+ *   - step (B) / Fig. 1 step (3): n_sw Metropolis sweeps of the switched
+ *     Hamiltonian H' of Eq. (4), colour by colour;
+ *   - the observables E (full H), M and the graph statistics of Sec. 3.2.
+ *
+ * Readings where the paper is silent (full list in the design notes):
+ *   - candidate bonds are generated per owner site by a Poisson process over the
+ *     cumulative bound rate (geometric skipping), then thinned by (1-P_ij)/pbar_ij;
+ *   - kappa == 1 makes a surviving bond "hard" (pseudo-interaction +inf for the
+ *     parallel state): both of its spins are frozen for the rest of the step;
+ *   - the initial N-colouring of KW is the row-major site index; the new colour of
+ *     a recoloured vertex is the smallest colour unused by its same-group neighbours;
+ *   - all randomness is Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) keyed by
+ *     (seed, chain_id) with counter (step, site, draw, tag).
+ *
+ * Compiled with -O2 -ffp-contract=off: every floating-point expression is evaluated
+ * exactly as written, in the order written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- parameters */
+typedef struct {
+  int32_t L, periodic, n_images, n_sw;
+  double J, D, T, kappa;
+  uint32_t seed, chain_id;
+} orc_params;
+
+typedef struct {
+  double E, E_exchange, E_dipolar;
+  int64_t M, n_edges;
+  int32_t delta_union, q, colors_used, kw_levels;
+  int64_t kw_rounds, accepted, attempts, near_ties;
+} orc_obs;
+
+enum { TAG_INIT = 1, TAG_SW = 2, TAG_TH = 3, TAG_MC = 4 };
+
+/* ---------------------------------------------------------------- Philox4x32-10
+ * Salmon et al. (SC'11), Sec. 3.2: ten rounds of two 32x32->64 multiplications
+ * with a Weyl-sequence key schedule. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform on (0,1): the top 52 bits of (hi:lo) as an integer k, u = (k + 1/2) 2^-52.
+ * Every value is exact, the smallest is 2^-53 and the largest 1 - 2^-53. */
+double orc_u52(uint32_t lo, uint32_t hi) {
+  uint64_t w = ((uint64_t)hi << 32) | (uint64_t)lo;
+  double k = (double)(w >> 12);
+  return (k + 0.5) * 0x1p-52;
+}
+
+static void draw(const orc_params* p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag,
+                 uint32_t out[4]) {
+  uint32_t ctr[4] = {c0, c1, c2, tag};
+  uint32_t key[2] = {p->seed, p->chain_id};
+  orc_philox(ctr, key, out);
+}
+
+/* ---------------------------------------------------------------- chain state */
+typedef struct {
+  orc_params p;
+  int L, N, K, hard;
+  double beta, inv_rate;
+  /* half-displacement table, sorted by (r^2, dy, dx) */
+  int32_t *hdx, *hdy;
+  double *Jm, *Cm, *theta, *delta;
+  int8_t* s;
+  /* switched-bond graph (both directions), rows ascending by neighbour */
+  int64_t n_edges, cap;
+  int32_t *sv_owner, *sv_nb, *sv_m; /* survivors in draw order */
+  int32_t *row_ptr, *col, *attr;
+  /* colouring */
+  int32_t delta_union, q, M;
+  int64_t kw_rounds;
+  int32_t* kw_rounds_level; /* [64] */
+  int32_t* color;
+  /* counters */
+  int64_t accepted, attempts, near_ties;
+} orc_chain;
+
+static int cmp_disp(const void* a, const void* b) {
+  const int32_t* u = (const int32_t*)a;
+  const int32_t* v = (const int32_t*)b;
+  int64_t ru = (int64_t)u[0] * u[0] + (int64_t)u[1] * u[1];
+  int64_t rv = (int64_t)v[0] * v[0] + (int64_t)v[1] * v[1];
+  if (ru != rv) return ru < rv ? -1 : 1;
+  if (u[1] != v[1]) return u[1] < v[1] ? -1 : 1;
+  if (u[0] != v[0]) return u[0] < v[0] ? -1 : 1;
+  return 0;
+}
+
+/* Dipolar coupling of one displacement: D / r^3, summed over the periodic images
+ * (nx outer, ny inner, both ascending) when the lattice is periodic. */
+static double coupling(const orc_params* p, int dx, int dy) {
+  if (!p->periodic) {
+    double r2 = (double)dx * (double)dx + (double)dy * (double)dy;
+    return p->D / (r2 * sqrt(r2));
+  }
+  double acc = 0.0;
+  int n = p->n_images, L = p->L;
+  for (int nx = -n; nx <= n; ++nx)
+    for (int ny = -n; ny <= n; ++ny) {
+      double X = (double)(dx + nx * L), Y = (double)(dy + ny * L);
+      double r2 = X * X + Y * Y;
+      if (r2 == 0.0) continue;
+      acc += p->D / (r2 * sqrt(r2));
+    }
+  return acc;
+}
+
+/* Partner of owner i through half-displacement m; returns -1 when the pair is not
+ * owned by i (outside an open lattice, or the other half of a self-conjugate
+ * displacement of a periodic lattice). */
+static int partner(const orc_chain* c, int i, int m) {
+  int L = c->L, x = i % L, y = i / L, dx = c->hdx[m], dy = c->hdy[m];
+  if (c->p.periodic) {
+    int h = L / 2;
+    if (dy == 0 && dx == h && x >= h) return -1;
+    if (dy == h && (dx == 0 || dx == h) && y >= h) return -1;
+    int jx = (x + dx + L) % L, jy = (y + dy) % L;
+    return jy * L + jx;
+  }
+  int jx = x + dx, jy = y + dy;
+  if (jx < 0 || jx >= L || jy >= L) return -1;
+  return jy * L + jx;
+}
+
+/* nearest neighbours in the order +x, -x, +y, -y; returns the count */
+static int neighbours(const orc_chain* c, int v, int nb[4]) {
+  int L = c->L, x = v % L, y = v / L, n = 0;
+  if (c->p.periodic) {
+    nb[0] = y * L + (x + 1) % L;
+    nb[1] = y * L + (x + L - 1) % L;
+    nb[2] = ((y + 1) % L) * L + x;
+    nb[3] = ((y + L - 1) % L) * L + x;
+    return 4;
+  }
+  if (x + 1 < L) nb[n++] = v + 1;
+  if (x > 0) nb[n++] = v - 1;
+  if (y + 1 < L) nb[n++] = v + L;
+  if (y > 0) nb[n++] = v - L;
+  return n;
+}
+
+void orc_destroy(orc_chain* c) {
+  if (!c) return;
+  free(c->hdx); free(c->hdy); free(c->Jm); free(c->Cm); free(c->theta); free(c->delta);
+  free(c->s); free(c->sv_owner); free(c->sv_nb); free(c->sv_m);
+  free(c->row_ptr); free(c->col); free(c->attr); free(c->kw_rounds_level); free(c->color);
+  free(c);
+}
+
+/* Returns NULL on invalid parameters. */
+orc_chain* orc_create(const orc_params* p, const int8_t* init_spins) {
+  if (p->L < 2 || p->T <= 0.0 || !(p->kappa >= 1.0) || p->n_sw < 0 || p->n_images < 0) return NULL;
+  if (p->periodic && (p->L < 4 || (p->L & 1))) return NULL;
+  orc_chain* c = (orc_chain*)calloc(1, sizeof(orc_chain));
+  c->p = *p;
+  c->L = p->L;
+  c->N = p->L * p->L;
+  c->hard = (p->kappa == 1.0);
+  c->beta = 1.0 / p->T;
+  c->inv_rate = p->T / (p->kappa + 1.0);
+  int L = c->L, N = c->N;
+
+  /* half-displacement set: each unordered pair of sites is reached from exactly one
+   * (owner, displacement) combination that passes partner(). */
+  int cap = p->periodic ? (L / 2 + 1) * L : 2 * L * L;
+  int32_t* d = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
+  int K = 0;
+  if (p->periodic) {
+    int h = L / 2;
+    for (int dy = 0; dy <= h; ++dy)
+      for (int dx = -h + 1; dx <= h; ++dx) {
+        int keep;
+        if (dy > 0 && dy < h) keep = 1;
+        else keep = (dx > 0) || (dy == h && dx == 0); /* dy==0: 0<dx<=h ; dy==h: 0<=dx<=h */
+        if (!keep) continue;
+        d[2 * K] = dx; d[2 * K + 1] = dy; ++K;
+      }
+  } else {
+    for (int dy = 0; dy < L; ++dy)
+      for (int dx = -(L - 1); dx < L; ++dx) {
+        if (dy == 0 && dx <= 0) continue;
+        d[2 * K] = dx; d[2 * K + 1] = dy; ++K;
+      }
+  }
+  qsort(d, (size_t)K, 2 * sizeof(int32_t), cmp_disp);
+  c->K = K;
+  c->hdx = (int32_t*)malloc(sizeof(int32_t) * K);
+  c->hdy = (int32_t*)malloc(sizeof(int32_t) * K);
+  c->Jm = (double*)malloc(sizeof(double) * K);
+  c->Cm = (double*)malloc(sizeof(double) * K);
+  c->theta = (double*)malloc(sizeof(double) * K);
+  c->delta = (double*)malloc(sizeof(double) * K);
+  double acc = 0.0;
+  for (int m = 0; m < K; ++m) {
+    c->hdx[m] = d[2 * m];
+    c->hdy[m] = d[2 * m + 1];
+    double Jd = coupling(p, c->hdx[m], c->hdy[m]);
+    c->Jm[m] = Jd;
+    acc += Jd;
+    c->Cm[m] = acc;
+    /* Eq. (2) with V = J s_i s_j and V^max = kappa J:
+     *   P(parallel) = exp(-beta (kappa-1) J), P(antiparallel) = exp(-beta (kappa+1) J).
+     * A candidate (probability 1-P(antiparallel)) survives with probability
+     * (1-P)/(1-P(antiparallel)): 1 for antiparallel, theta for parallel. */
+    double em = expm1(-c->beta * (p->kappa + 1.0) * Jd);
+    double ep = expm1(-c->beta * (p->kappa - 1.0) * Jd);
+    c->theta[m] = c->hard ? 0.0 : ep / em;
+    /* Eq. (3): Vbar(s) = J s - T log(1 - P(s)); delta = Vbar(+1) - Vbar(-1). */
+    c->delta[m] = c->hard ? INFINITY : 2.0 * Jd + p->T * log(em / ep);
+  }
+  free(d);
+
+  c->s = (int8_t*)malloc((size_t)N);
+  for (int v = 0; v < N; ++v) {
+    if (init_spins) { c->s[v] = init_spins[v] > 0 ? 1 : -1; continue; }
+    uint32_t w[4];
+    draw(p, 0u, (uint32_t)v, 0u, TAG_INIT, w);
+    c->s[v] = (w[0] >> 31) ? -1 : 1;
+  }
+  c->cap = 1024;
+  c->sv_owner = (int32_t*)malloc(sizeof(int32_t) * c->cap);
+  c->sv_nb = (int32_t*)malloc(sizeof(int32_t) * c->cap);
+  c->sv_m = (int32_t*)malloc(sizeof(int32_t) * c->cap);
+  c->row_ptr = (int32_t*)calloc((size_t)N + 1, sizeof(int32_t));
+  c->col = (int32_t*)malloc(sizeof(int32_t) * 2 * c->cap);
+  c->attr = (int32_t*)malloc(sizeof(int32_t) * 2 * c->cap);
+  c->kw_rounds_level = (int32_t*)calloc(64, sizeof(int32_t));
+  c->color = (int32_t*)calloc((size_t)N, sizeof(int32_t));
+  return c;
+}
+
+static void push_survivor(orc_chain* c, int i, int j, int m) {
+  if (c->n_edges == c->cap) {
+    c->cap *= 2;
+    c->sv_owner = (int32_t*)realloc(c->sv_owner, sizeof(int32_t) * c->cap);
+    c->sv_nb = (int32_t*)realloc(c->sv_nb, sizeof(int32_t) * c->cap);
+    c->sv_m = (int32_t*)realloc(c->sv_m, sizeof(int32_t) * c->cap);
+    c->col = (int32_t*)realloc(c->col, sizeof(int32_t) * 2 * c->cap);
+    c->attr = (int32_t*)realloc(c->attr, sizeof(int32_t) * 2 * c->cap);
+  }
+  c->sv_owner[c->n_edges] = i;
+  c->sv_nb[c->n_edges] = j;
+  c->sv_m[c->n_edges] = m;
+  c->n_edges++;
+}
+
+static int near(double a, double b) { return fabs(a - b) <= 1e-12 * fabs(b); }
+
+/* ------------------------------------------------------------ step (A): switching
+ * Every pair (i, i+d_m) is a candidate with probability pbar_m = 1 - exp(-lambda_m),
+ * lambda_m = (kappa+1) beta J_m, independently: the candidates of owner i are the
+ * intervals (C_{m-1}, C_m] of the cumulative coupling hit by a Poisson process of
+ * rate (kappa+1) beta, scanned from the start of the table.  A candidate then
+ * survives with probability (1 - P_ij(s)) / pbar_m, which makes the overall
+ * survival probability exactly 1 - P_ij as Eq. (1) requires. */
+int orc_switch(orc_chain* c, uint64_t t) {
+  c->n_edges = 0;
+  const double Ctop = c->Cm[c->K - 1];
+  for (int i = 0; i < c->N; ++i) {
+    int pos = -1, k = 0;
+    double Cpos = 0.0;
+    for (;; ++k) {
+      uint32_t w[4];
+      draw(&c->p, (uint32_t)t, (uint32_t)i, (uint32_t)(k >> 1), TAG_SW, w);
+      double u1 = (k & 1) ? orc_u52(w[2], w[3]) : orc_u52(w[0], w[1]);
+      double target = Cpos + (-log(u1)) * c->inv_rate;
+      if (near(target, Ctop)) c->near_ties++;
+      if (target > Ctop) break;
+      int lo = pos + 1, hi = c->K - 1; /* smallest m > pos with C_m >= target */
+      while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (c->Cm[mid] >= target) hi = mid; else lo = mid + 1;
+      }
+      int m = lo;
+      if (near(target, c->Cm[m]) || (m - 1 > pos && near(target, c->Cm[m - 1]))) c->near_ties++;
+      int j = partner(c, i, m);
+      if (j >= 0) {
+        int keep = (c->s[i] != c->s[j]);
+        if (!keep && !c->hard) {
+          uint32_t w2[4];
+          draw(&c->p, (uint32_t)t, (uint32_t)i, (uint32_t)k, TAG_TH, w2);
+          keep = orc_u52(w2[0], w2[1]) < c->theta[m];
+        }
+        if (keep) push_survivor(c, i, j, m);
+      }
+      pos = m;
+      Cpos = c->Cm[m];
+    }
+  }
+  /* both directions of every surviving bond, rows ascending by neighbour index */
+  int N = c->N;
+  memset(c->row_ptr, 0, sizeof(int32_t) * ((size_t)N + 1));
+  for (int64_t e = 0; e < c->n_edges; ++e) {
+    c->row_ptr[c->sv_owner[e] + 1]++;
+    c->row_ptr[c->sv_nb[e] + 1]++;
+  }
+  for (int v = 0; v < N; ++v) c->row_ptr[v + 1] += c->row_ptr[v];
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  memcpy(fill, c->row_ptr, sizeof(int32_t) * (size_t)N);
+  for (int64_t e = 0; e < c->n_edges; ++e) {
+    int a = c->sv_owner[e], b = c->sv_nb[e], m = c->sv_m[e];
+    c->col[fill[a]] = b; c->attr[fill[a]] = m; fill[a]++;
+    c->col[fill[b]] = a; c->attr[fill[b]] = m; fill[b]++;
+  }
+  free(fill);
+  for (int v = 0; v < N; ++v) { /* insertion sort of each (short) row */
+    for (int x = c->row_ptr[v] + 1; x < c->row_ptr[v + 1]; ++x) {
+      int32_t kc = c->col[x], ka = c->attr[x];
+      int y = x - 1;
+      while (y >= c->row_ptr[v] && c->col[y] > kc) {
+        c->col[y + 1] = c->col[y]; c->attr[y + 1] = c->attr[y]; --y;
+      }
+      c->col[y + 1] = kc; c->attr[y + 1] = ka;
+    }
+  }
+  return 0;
+}
+
+/* distinct neighbours of v in the union of the exchange lattice and the surviving
+ * bonds; returns the count */
+static int union_neighbours(const orc_chain* c, int v, int32_t* out, int cap) {
+  int nb[4], n = neighbours(c, v, nb), cnt = 0;
+  for (int a = 0; a < n; ++a) {
+    int dup = 0;
+    for (int b = 0; b < cnt; ++b) dup |= (out[b] == nb[a]);
+    if (!dup && cnt < cap) out[cnt++] = nb[a];
+  }
+  for (int x = c->row_ptr[v]; x < c->row_ptr[v + 1]; ++x) {
+    int dup = 0;
+    for (int b = 0; b < cnt; ++b) dup |= (out[b] == c->col[x]);
+    if (!dup && cnt < cap) out[cnt++] = c->col[x];
+  }
+  return cnt;
+}
+
+/* ---------------------------------------------------- Fig. 1 step (2): colouring
+ * Sec. 2.3.3: level-0 groups of q = Delta+1 consecutive initial colours (initial
+ * colour = site index), so vertex v starts in group v/q with colour v mod q inside
+ * it.  Level p unites pairs of groups; the upper half (bit p-1 of v/q set) carries
+ * colours q..2q-1 and is reduced back into 0..q-1 by colour-reduction rounds
+ * (Sec. 2.3.2, rule (2)'): in a round every pending vertex whose colour exceeds
+ * the colour of every pending neighbour of its group takes the smallest colour in
+ * 0..q-1 that no neighbour of its group holds.  All decisions of a round read the
+ * colours of the previous round (synchronous communication, Sec. 2.3.1). */
+int orc_color(orc_chain* c) {
+  int N = c->N, maxdeg = 0;
+  int32_t nbuf[4096];
+  for (int v = 0; v < N; ++v) {
+    int d = union_neighbours(c, v, nbuf, 4096);
+    if (d > maxdeg) maxdeg = d;
+  }
+  int q = maxdeg + 1;
+  c->delta_union = maxdeg;
+  c->q = q;
+  int groups = (N + q - 1) / q, M = 0;
+  while ((1 << M) < groups) ++M;
+  c->M = M;
+  c->kw_rounds = 0;
+  memset(c->kw_rounds_level, 0, 64 * sizeof(int32_t));
+  int32_t* cur = c->color;
+  int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  uint8_t* pend = (uint8_t*)malloc((size_t)N);
+  uint8_t* npend = (uint8_t*)malloc((size_t)N);
+  uint8_t* used = (uint8_t*)malloc((size_t)q);
+  for (int v = 0; v < N; ++v) cur[v] = v % q;
+  for (int p = 1; p <= M; ++p) {
+    int npending = 0;
+    for (int v = 0; v < N; ++v) {
+      pend[v] = (uint8_t)(((v / q) >> (p - 1)) & 1);
+      if (pend[v]) { cur[v] += q; ++npending; }
+    }
+    int rounds = 0;
+    while (npending > 0) {
+      ++rounds;
+      memcpy(nxt, cur, sizeof(int32_t) * (size_t)N);
+      memcpy(npend, pend, (size_t)N);
+      for (int v = 0; v < N; ++v) {
+        if (!pend[v]) continue;
+        int grp = (v / q) >> p;
+        int d = union_neighbours(c, v, nbuf, 4096);
+        int localmax = 1;
+        memset(used, 0, (size_t)q);
+        for (int a = 0; a < d; ++a) {
+          int u = nbuf[a];
+          if (((u / q) >> p) != grp) continue;
+          if (pend[u] && cur[u] > cur[v]) localmax = 0;
+          if (cur[u] < q) used[cur[u]] = 1;
+        }
+        if (!localmax) continue;
+        int nc = 0;
+        while (nc < q && used[nc]) ++nc;
+        if (nc == q) { free(nxt); free(pend); free(npend); free(used); return -1; }
+        nxt[v] = nc;
+        npend[v] = 0;
+        --npending;
+      }
+      memcpy(cur, nxt, sizeof(int32_t) * (size_t)N);
+      memcpy(pend, npend, (size_t)N);
+    }
+    c->kw_rounds_level[p < 64 ? p : 63] = rounds;
+    c->kw_rounds += rounds;
+  }
+  free(nxt); free(pend); free(npend); free(used);
+  return 0;
+}
+
+/* ------------------------------------------------- step (B): Metropolis on H'
+ * One MC step is one trial per spin (Sec. 2.1), taken colour by colour.  Flipping
+ * s_v changes H' by s_v h_v, h_v = 2J sum_NN s_u - sum_bonds delta_m s_u, where
+ * delta_m = Vbar(+1) - Vbar(-1).  With kappa == 1 a bond's parallel state has
+ * infinite pseudo-energy, so a spin carrying a surviving bond never flips. */
+int orc_sweep(orc_chain* c, uint64_t t, int n_sw) {
+  int N = c->N;
+  for (int s = 0; s < n_sw; ++s)
+    for (int col = 0; col < c->q; ++col)
+      for (int v = 0; v < N; ++v) {
+        if (c->color[v] != col) continue;
+        c->attempts++;
+        int b0 = c->row_ptr[v], b1 = c->row_ptr[v + 1];
+        if (c->hard && b1 > b0) continue;
+        int nb[4], n = neighbours(c, v, nb), nn = 0;
+        for (int a = 0; a < n; ++a) nn += c->s[nb[a]];
+        double h = (2.0 * c->p.J) * (double)nn;
+        for (int x = b0; x < b1; ++x) {
+          double dm = c->delta[c->attr[x]];
+          h = c->s[c->col[x]] > 0 ? h - dm : h + dm;
+        }
+        double dE = c->s[v] > 0 ? h : -h;
+        int acc = 1;
+        if (dE > 0.0) {
+          uint32_t w[4];
+          draw(&c->p, (uint32_t)t, (uint32_t)v, (uint32_t)s, TAG_MC, w);
+          double u = orc_u52(w[0], w[1]);
+          double pr = exp(-c->beta * dE);
+          if (fabs(u - pr) < 1e-12) c->near_ties++;
+          acc = u < pr;
+        }
+        if (acc) { c->s[v] = (int8_t)-c->s[v]; c->accepted++; }
+      }
+  return 0;
+}
+
+int orc_step(orc_chain* c, uint64_t t) {
+  if (orc_switch(c, t)) return -1;
+  if (orc_color(c)) return -1;
+  return orc_sweep(c, t, c->p.n_sw);
+}
+
+/* ------------------------------------------------------------- observables
+ * E = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j, the second sum taken pair by
+ * pair through the owner rule (O(N K): used for small lattices; the Python layer
+ * evaluates the same sum from FFT autocorrelations for large ones). */
+void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
+  int N = c->N;
+  int64_t M = 0, ex = 0;
+  for (int v = 0; v < N; ++v) {
+    M += c->s[v];
+    int L = c->L, x = v % L, y = v / L;
+    if (c->p.periodic) {
+      ex += c->s[v] * c->s[y * L + (x + 1) % L];
+      ex += c->s[v] * c->s[((y + 1) % L) * L + x];
+    } else {
+      if (x + 1 < L) ex += c->s[v] * c->s[v + 1];
+      if (y + 1 < L) ex += c->s[v] * c->s[v + L];
+    }
+  }
+  double Edip = 0.0;
+  if (with_dipolar) {
+    for (int m = 0; m < c->K; ++m) {
+      int64_t cm = 0;
+      for (int i = 0; i < N; ++i) {
+        int j = partner(c, i, m);
+        if (j >= 0) cm += c->s[i] * c->s[j];
+      }
+      Edip += c->Jm[m] * (double)cm;
+    }
+  }
+  int colors_used = 0;
+  if (c->q > 0) {
+    uint8_t* seen = (uint8_t*)calloc((size_t)c->q, 1);
+    for (int v = 0; v < N; ++v) if (c->color[v] >= 0 && c->color[v] < c->q) seen[c->color[v]] = 1;
+    for (int a = 0; a < c->q; ++a) colors_used += seen[a];
+    free(seen);
+  }
+  o->E_exchange = -c->p.J * (double)ex;
+  o->E_dipolar = Edip;
+  o->E = o->E_exchange + Edip;
+  o->M = M;
+  o->n_edges = c->n_edges;
+  o->delta_union = c->delta_union;
+  o->q = c->q;
+  o->colors_used = colors_used;
+  o->kw_levels = c->M;
+  o->kw_rounds = c->kw_rounds;
+  o->accepted = c->accepted;
+  o->attempts = c->attempts;
+  o->near_ties = c->near_ties;
+}
+
+/* ----------------------------------------------------------- accessors */
+int orc_N(const orc_chain* c) { return c->N; }
+int orc_K(const orc_chain* c) { return c->K; }
+int64_t orc_n_edges(const orc_chain* c) { return c->n_edges; }
+void orc_get_spins(const orc_chain* c, int8_t* out) { memcpy(out, c->s, (size_t)c->N); }
+void orc_set_spins(orc_chain* c, const int8_t* in) {
+  for (int v = 0; v < c->N; ++v) c->s[v] = in[v] > 0 ? 1 : -1;
+}
+void orc_get_tables(const orc_chain* c, int32_t* dx, int32_t* dy, double* J, double* C,
+                    double* theta, double* delta) {
+  size_t K = (size_t)c->K;
+  if (dx) memcpy(dx, c->hdx, K * sizeof(int32_t));
+  if (dy) memcpy(dy, c->hdy, K * sizeof(int32_t));
+  if (J) memcpy(J, c->Jm, K * sizeof(double));
+  if (C) memcpy(C, c->Cm, K * sizeof(double));
+  if (theta) memcpy(theta, c->theta, K * sizeof(double));
+  if (delta) memcpy(delta, c->delta, K * sizeof(double));
+}
+/* survivors in draw order (owner ascending, then draw order) */
+void orc_get_survivors(const orc_chain* c, int32_t* owner, int32_t* nb, int32_t* m) {
+  size_t E = (size_t)c->n_edges;
+  memcpy(owner, c->sv_owner, E * sizeof(int32_t));
+  memcpy(nb, c->sv_nb, E * sizeof(int32_t));
+  memcpy(m, c->sv_m, E * sizeof(int32_t));
+}
+void orc_get_csr(const orc_chain* c, int32_t* row_ptr, int32_t* col, int32_t* attr) {
+  memcpy(row_ptr, c->row_ptr, ((size_t)c->N + 1) * sizeof(int32_t));
+  memcpy(col, c->col, 2 * (size_t)c->n_edges * sizeof(int32_t));
+  memcpy(attr, c->attr, 2 * (size_t)c->n_edges * sizeof(int32_t));
+}
+void orc_get_colors(const orc_chain* c, int32_t* out) { memcpy(out, c->color, (size_t)c->N * sizeof(int32_t)); }
+void orc_get_kw_rounds(const orc_chain* c, int32_t* out64) { memcpy(out64, c->kw_rounds_level, 64 * sizeof(int32_t)); }
+int orc_partner(const orc_chain* c, int i, int m) { return partner(c, i, m); }
+void orc_reset_counters(orc_chain* c) { c->accepted = c->attempts = c->near_ties = 0; }
+
+/* Per-pair survival counts over n_steps switching passes with the spins held fixed
+ * (statistical test helper): counts[i*K + m] += 1 for every survivor (i, m). */
+void orc_survival_counts(orc_chain* c, uint64_t t0, int n_steps, int32_t* counts) {
+  for (int s = 0; s < n_steps; ++s) {
+    orc_switch(c, t0 + (uint64_t)s);
+    for (int64_t e = 0; e < c->n_edges; ++e)
+      counts[(size_t)c->sv_owner[e] * (size_t)c->K + (size_t)c->sv_m[e]]++;
+  }
+}
+
+/* Runs n_steps SCO steps from step t0 and records (E, M) after every thin-th step,
+ * E recomputed from its definition (small lattices only).  Returns the next step
+ * index. */
+uint64_t orc_run_record(orc_chain* c, uint64_t t0, int n_steps, int thin, double* E_out,
+                        int64_t* M_out) {
+  uint64_t t = t0;
+  int rec = 0;
+  for (int s = 0; s < n_steps; ++s, ++t) {
+    orc_step(c, t);
+    if (thin > 0 && (s + 1) % thin == 0) {
+      orc_obs o;
+      orc_observables(c, &o, 1);
+      E_out[rec] = o.E;
+      M_out[rec] = o.M;
+      ++rec;
+    }
+  }
+  return t;
+}
