@@ -295,7 +295,7 @@ int orc_switch(orc_chain* c, uint64_t t) {
   for (int i = 0; i < c->N; ++i) {
     int pos = -1, k = 0;
     double Cpos = 0.0;
-    for (;; ++k) {
+    for (; pos < c->K - 1; ++k) { /* no candidate lies beyond the last table entry */
       uint32_t w[4];
       draw(&c->p, (uint32_t)t, (uint32_t)i, (uint32_t)(k >> 1), TAG_SW, w);
       double u1 = (k & 1) ? orc_u52(w[2], w[3]) : orc_u52(w[0], w[1]);
