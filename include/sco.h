@@ -1,0 +1,150 @@
+/*
+ * sco.h -- C-ABI of libsco, the MI355X (gfx950) stochastic-cutoff Monte-Carlo step.
+ *
+ * Method: Endo, Toga & Sasaki, "Parallelized Stochastic Cutoff Method for
+ * Long-Range Interacting Systems".  One SCO step of a chain is
+ *   (1) switching of every dipolar bond to 0 or to its pseudo-interaction
+ *       (Sec. 2.1, Eqs. 1-3; Fig. 1 step (1)),
+ *   (2) Kuhn-Wattenhofer colouring of the graph of surviving bonds united with
+ *       the never-switched nearest-neighbour exchange bonds (Sec. 2.3, Eq. 5;
+ *       Fig. 1 step (2)),
+ *   (3) n_sw Metropolis sweeps of the switched Hamiltonian H' (Eq. 4), one
+ *       colour class at a time (Fig. 1 step (3)).
+ * The model is the perpendicular-Ising form of Eq. (6):
+ *     H = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j,  s_i = +-1,
+ * with J_ij = D / r_ij^3 on an open L x L lattice, or J_ij summed over the
+ * periodic images |n_x|, |n_y| <= n_images of a periodic one.
+ *
+ * Conventions shared by every call
+ *   - All device memory belongs to the caller: one workspace of
+ *     sco_workspace_size() bytes (256-byte aligned) handed to sco_init.  The
+ *     library never allocates device memory after sco_init and never frees the
+ *     caller's memory.  sco_init allocates a small pinned host staging buffer.
+ *   - Every call is ordered on the HIP stream given to sco_init (`stream` is a
+ *     hipStream_t passed as void*; NULL is the default stream).  Only
+ *     sco_observables, sco_get_* , sco_set_spins and sco_init synchronise it.
+ *   - A context is used by one host thread at a time.  Several contexts may
+ *     coexist; they share nothing.
+ *   - Return value: SCO_OK (0) or a negative SCO_E* code; sco_strerror() names it.
+ *     Device-side conditions (edge capacity exceeded, a bounded wait that timed
+ *     out) are raised as flags and reported by the next synchronising call.
+ *   - Sites are numbered row-major, v = y * L + x; spins are int8 +1 / -1.
+ *   - Randomness: Philox4x32-10 (Salmon et al., SC'11), key (seed, chain_id),
+ *     counter (step, site, draw, tag).  A chain is a pure function of its
+ *     parameters, its initial spins and the step indices it was given.
+ */
+#ifndef SCO_H
+#define SCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCO_OK 0
+#define SCO_EINVAL (-1)    /* invalid argument or parameter */
+#define SCO_EHIP (-2)      /* a HIP runtime call failed */
+#define SCO_EOVERFLOW (-3) /* surviving bonds exceeded the edge capacity: the step is invalid */
+#define SCO_EINTERNAL (-4) /* an invariant failed or a bounded device wait timed out */
+#define SCO_ENOSPC (-5)    /* the workspace is smaller than sco_workspace_size() */
+
+/* Parameters of one Markov chain. */
+typedef struct {
+  int32_t L;          /* linear size; periodic lattices need even L >= 4, open L >= 2 */
+  int32_t periodic;   /* 1: periodic boundaries with image-summed couplings; 0: open */
+  int32_t n_images;   /* periodic image box half-width (8 in the reference workloads) */
+  int32_t n_sw;       /* Metropolis sweeps per SCO step (Sec. 2.1 step (B)); >= 0 */
+  double J;           /* nearest-neighbour exchange constant (> 0 ferromagnetic) */
+  double D;           /* dipolar constant, J_ij = D / r^3 */
+  double T;           /* temperature, beta = 1 / T; > 0 */
+  double kappa;       /* V^max = kappa * J_ij (Eq. 2 needs V^max >= max V); >= 1 */
+  uint32_t seed;      /* Philox key word 0 */
+  uint32_t chain_id;  /* Philox key word 1 */
+  int32_t precision;  /* 0: FP64 decisions; 1: FP32 accumulation + FP64 recheck (same chain) */
+  int32_t edge_factor;/* directed-bond capacity per site (0: default 8) */
+} sco_chain_params;
+
+/* Per-chain observables and counters, FP64 / exact integers. */
+typedef struct {
+  double E;           /* full Hamiltonian of the current spins */
+  double E_exchange;  /* -J sum_<ij> s_i s_j (an exact integer times J) */
+  double E_dipolar;   /* sum_{i<j} J_ij s_i s_j */
+  int64_t M;          /* sum_i s_i */
+  int64_t n_edges;    /* surviving bonds of the last switching (undirected) */
+  int32_t delta_union;/* maximum degree of the union graph coloured last */
+  int32_t q;          /* palette size delta_union + 1 */
+  int32_t colors_used;/* colours holding at least one site */
+  int32_t kw_levels;  /* KW levels M = ceil(log2(ceil(N / q))) */
+  int64_t kw_rounds;  /* synchronous rounds of rule (2)' summed over the levels */
+  int64_t accepted;   /* accepted flips since sco_init (or the last counter reset) */
+  int64_t attempts;   /* Metropolis trials since sco_init */
+  int64_t rechecks;   /* FP32 decisions recomputed in FP64 (precision 1) */
+  int64_t flags;      /* device flags seen (bit 0 overflow, bit 1 wait timeout) */
+} sco_obs;
+
+typedef struct sco_ctx sco_ctx;
+
+/* Bytes of device workspace needed for n_chains chains (host-only computation).
+ * Returns SCO_EINVAL on invalid parameters. */
+int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* bytes);
+
+/* Creates a context over the caller's workspace.  Builds, per distinct lattice,
+ * the half-displacement table sorted by (r^2, dy, dx), the couplings J(d)
+ * (image sums on the GPU), the cumulative couplings and, per chain, the switching
+ * and pseudo-interaction columns (Eqs. 2-3); then the initial spins: copied from
+ * dev_init_spins (int8, the chains' sites concatenated in chain order, may be
+ * NULL) or drawn from Philox.  Synchronises `stream`. */
+int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
+             size_t workspace_bytes, const int8_t* dev_init_spins, void* stream);
+
+/* Step (1) for every chain: switch all dipolar bonds for SCO step `step` and
+ * assemble the symmetric CSR of the survivors (rows ascending by neighbour). */
+int sco_switch(sco_ctx* ctx, uint64_t step);
+
+/* Step (2): KW colouring of the union graph, then bucketing of the sites by colour. */
+int sco_color(sco_ctx* ctx);
+
+/* Step (3): n_sw colour-ordered Metropolis sweeps with the RNG counters of `step`. */
+int sco_sweep(sco_ctx* ctx, uint64_t step, int n_sw);
+
+/* Steps (1)-(3) with each chain's own n_sw. */
+int sco_step(sco_ctx* ctx, uint64_t step);
+
+/* Runs steps first_step .. first_step + n_steps - 1 back to back. */
+int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
+
+/* Observables of every chain into host_out[n_chains]; synchronises. */
+int sco_observables(sco_ctx* ctx, sco_obs* host_out);
+
+/* Checkpoint / resume: spins of one chain (N int8 values) to / from host memory. */
+int sco_get_spins(sco_ctx* ctx, int chain, int8_t* host_out);
+int sco_set_spins(sco_ctx* ctx, int chain, const int8_t* host_in);
+
+/* The last switched graph of one chain, in site numbers local to the chain:
+ * row_ptr[N+1], col[n_dir], attr[n_dir] (half-displacement index of the bond),
+ * colors[N]; any pointer may be NULL; *n_dir receives 2 * n_edges. */
+int sco_get_graph(sco_ctx* ctx, int chain, int32_t* row_ptr, int32_t* col, int32_t* attr,
+                  int32_t* colors, int64_t* n_dir);
+
+/* The displacement table of one chain: K entries of dx, dy, J, C (cumulative J),
+ * theta (survival ratio of a parallel candidate) and delta (Vbar(+1) - Vbar(-1));
+ * any pointer may be NULL; *K receives the table length. */
+int sco_get_tables(sco_ctx* ctx, int chain, int32_t* K, int32_t* dx, int32_t* dy, double* J,
+                   double* C, double* theta, double* delta);
+
+/* Device time of the phases of the last sco_step/sco_run call, in ms:
+ * out[0] switching + assembly, out[1] colouring, out[2] sweeps (events on the stream). */
+int sco_phase_times(sco_ctx* ctx, float* out3);
+
+/* Sets counters (accepted, attempts, rechecks, flags) of every chain to zero. */
+int sco_reset_counters(sco_ctx* ctx);
+
+int sco_destroy(sco_ctx* ctx);
+const char* sco_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCO_H */

@@ -1,0 +1,92 @@
+"""ctypes declarations of the libsco C-ABI (include/sco.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsco.so")
+
+SCO_OK, SCO_EINVAL, SCO_EHIP, SCO_EOVERFLOW, SCO_EINTERNAL, SCO_ENOSPC = 0, -1, -2, -3, -4, -5
+
+EXPORTS = [
+    "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
+    "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
+    "sco_phase_times", "sco_reset_counters", "sco_destroy", "sco_strerror",
+]
+
+
+class ChainParamsC(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32), ("periodic", ctypes.c_int32), ("n_images", ctypes.c_int32),
+        ("n_sw", ctypes.c_int32),
+        ("J", ctypes.c_double), ("D", ctypes.c_double), ("T", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("seed", ctypes.c_uint32), ("chain_id", ctypes.c_uint32),
+        ("precision", ctypes.c_int32), ("edge_factor", ctypes.c_int32),
+    ]
+
+
+class ObsC(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_double), ("E_exchange", ctypes.c_double), ("E_dipolar", ctypes.c_double),
+        ("M", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+        ("delta_union", ctypes.c_int32), ("q", ctypes.c_int32), ("colors_used", ctypes.c_int32),
+        ("kw_levels", ctypes.c_int32),
+        ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
+        ("rechecks", ctypes.c_int64), ("flags", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ScoError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {lib().sco_strerror(code).decode()} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises when it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsco.so not found at {LIB_PATH}: build it with "
+                           "`python -m paper_1503_03295_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, u64 = ctypes.c_int, ctypes.c_uint64
+    sig = {
+        "sco_workspace_size": ([ctypes.POINTER(ChainParamsC), i32, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "sco_init": ([ctypes.POINTER(P), ctypes.POINTER(ChainParamsC), i32, P, ctypes.c_size_t, P, P], i32),
+        "sco_switch": ([P, u64], i32),
+        "sco_color": ([P], i32),
+        "sco_sweep": ([P, u64, i32], i32),
+        "sco_step": ([P, u64], i32),
+        "sco_run": ([P, u64, i32], i32),
+        "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),
+        "sco_get_spins": ([P, i32, P], i32),
+        "sco_set_spins": ([P, i32, P], i32),
+        "sco_get_graph": ([P, i32, P, P, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
+        "sco_get_tables": ([P, i32, ctypes.POINTER(ctypes.c_int32), P, P, P, P, P, P], i32),
+        "sco_phase_times": ([P, ctypes.POINTER(ctypes.c_float)], i32),
+        "sco_reset_counters": ([P], i32),
+        "sco_destroy": ([P], i32),
+        "sco_strerror": ([i32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(code: int, what: str) -> None:
+    if code != SCO_OK:
+        raise ScoError(code, what)

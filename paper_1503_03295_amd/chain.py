@@ -1,0 +1,153 @@
+"""Python face of libsco: argument marshalling only.
+
+PyTorch provides the device workspace and the stream; every step of the method
+runs in the HIP kernels behind the C-ABI (include/sco.h).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ChainParamsC, ObsC, check, lib
+
+
+@dataclass
+class ChainParams:
+    """One Markov chain: L x L perpendicular-Ising dipolar lattice (Eq. 6 with
+    s_i = +-1 along z), temperature T, V^max = kappa J_ij, n_sw sweeps per step."""
+    L: int
+    periodic: bool
+    T: float
+    J: float = 1.0
+    D: float = 0.1
+    kappa: float = 1.0
+    n_images: int = 8
+    n_sw: int = 1
+    seed: int = 1
+    chain_id: int = 0
+    precision: int = 0  # 0 FP64, 1 FP32 accumulation + FP64 recheck
+    edge_factor: int = 0
+
+    def to_c(self) -> ChainParamsC:
+        return ChainParamsC(self.L, int(self.periodic), self.n_images, self.n_sw, self.J, self.D,
+                            self.T, self.kappa, self.seed & 0xFFFFFFFF, self.chain_id & 0xFFFFFFFF,
+                            self.precision, self.edge_factor)
+
+
+def workspace_size(params: list[ChainParams]) -> int:
+    arr = (ChainParamsC * len(params))(*[p.to_c() for p in params])
+    n = ctypes.c_size_t(0)
+    check(lib().sco_workspace_size(arr, len(params), ctypes.byref(n)), "sco_workspace_size")
+    return int(n.value)
+
+
+class SCO:
+    """A batch of independent SCO chains resident on one GPU."""
+
+    def __init__(self, params: list[ChainParams] | ChainParams, device: str | int = "cuda",
+                 init_spins: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+        if isinstance(params, ChainParams):
+            params = [params]
+        self.params = list(params)
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("libsco runs on a GPU device")
+        self._carr = (ChainParamsC * len(self.params))(*[p.to_c() for p in self.params])
+        self.nbytes = workspace_size(self.params)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ip = None
+        if init_spins is not None:
+            self._init = init_spins.to(device=self.device, dtype=torch.int8).contiguous()
+            ip = ctypes.c_void_p(self._init.data_ptr())
+        h = ctypes.c_void_p()
+        check(lib().sco_init(ctypes.byref(h), self._carr, len(self.params),
+                             ctypes.c_void_p(self.workspace.data_ptr()), self.nbytes, ip,
+                             ctypes.c_void_p(self.stream.cuda_stream)), "sco_init")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().sco_destroy(h)
+            self._h = None
+
+    def close(self) -> None:
+        self.__del__()
+
+    @property
+    def n_chains(self) -> int:
+        return len(self.params)
+
+    # -- the step
+    def switch(self, step: int) -> None:
+        check(lib().sco_switch(self._h, step), "sco_switch")
+
+    def color(self) -> None:
+        check(lib().sco_color(self._h), "sco_color")
+
+    def sweep(self, step: int, n_sw: int) -> None:
+        check(lib().sco_sweep(self._h, step, n_sw), "sco_sweep")
+
+    def step(self, step: int) -> None:
+        check(lib().sco_step(self._h, step), "sco_step")
+
+    def run(self, first_step: int, n_steps: int) -> None:
+        check(lib().sco_run(self._h, first_step, n_steps), "sco_run")
+
+    # -- results
+    def observables(self) -> list[dict]:
+        out = (ObsC * self.n_chains)()
+        check(lib().sco_observables(self._h, out), "sco_observables")
+        return [o.as_dict() for o in out]
+
+    def spins(self, chain: int = 0) -> np.ndarray:
+        p = self.params[chain]
+        out = np.empty(p.L * p.L, np.int8)
+        check(lib().sco_get_spins(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)), "sco_get_spins")
+        return out
+
+    def set_spins(self, chain: int, spins: np.ndarray) -> None:
+        a = np.ascontiguousarray(spins, dtype=np.int8)
+        p = self.params[chain]
+        if a.size != p.L * p.L:
+            raise ValueError("wrong number of spins")
+        check(lib().sco_set_spins(self._h, chain, a.ctypes.data_as(ctypes.c_void_p)), "sco_set_spins")
+
+    def graph(self, chain: int = 0):
+        p = self.params[chain]
+        N = p.L * p.L
+        nd = ctypes.c_int64(0)
+        check(lib().sco_get_graph(self._h, chain, None, None, None, None, ctypes.byref(nd)), "sco_get_graph")
+        rp = np.empty(N + 1, np.int32)
+        col = np.empty(max(nd.value, 1), np.int32)
+        at = np.empty(max(nd.value, 1), np.int32)
+        colors = np.empty(N, np.int32)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(lib().sco_get_graph(self._h, chain, ptr(rp), ptr(col), ptr(at), ptr(colors), ctypes.byref(nd)),
+              "sco_get_graph")
+        return rp, col[: nd.value], at[: nd.value], colors
+
+    def tables(self, chain: int = 0) -> dict:
+        K = ctypes.c_int32(0)
+        check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), None, None, None, None, None, None),
+              "sco_get_tables")
+        n = K.value
+        dx = np.empty(n, np.int32); dy = np.empty(n, np.int32)
+        J = np.empty(n); C = np.empty(n); th = np.empty(n); de = np.empty(n)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), ptr(dx), ptr(dy), ptr(J), ptr(C),
+                                   ptr(th), ptr(de)), "sco_get_tables")
+        return {"dx": dx, "dy": dy, "J": J, "C": C, "theta": th, "delta": de}
+
+    def phase_times(self) -> tuple[float, float, float]:
+        out = (ctypes.c_float * 3)()
+        check(lib().sco_phase_times(self._h, out), "sco_phase_times")
+        return tuple(out)
+
+    def reset_counters(self) -> None:
+        check(lib().sco_reset_counters(self._h), "sco_reset_counters")

@@ -1,0 +1,652 @@
+// sco_api.cpp -- host runtime of libsco: parameter checks, workspace layout, the
+// displacement tables, launches and read-backs.  See include/sco.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sco.h"
+#include "sco_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kNB = 1 << SCO_GUIDE_BITS;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t halfset_size(int L, int periodic) {
+  return periodic ? static_cast<int64_t>(L) * L / 2 + 1 : 2LL * L * (L - 1);
+}
+
+bool valid(const sco_chain_params& p) {
+  if (p.L < 2 || p.L > 16384) return false;
+  if (p.periodic && (p.L < 4 || (p.L & 1))) return false;
+  if (!(p.T > 0.0) || !(p.kappa >= 1.0) || !(p.J > 0.0) || !(p.D > 0.0)) return false;
+  if (!std::isfinite(p.T) || !std::isfinite(p.kappa) || !std::isfinite(p.J) || !std::isfinite(p.D)) return false;
+  if (p.n_sw < 0 || p.n_images < 0 || p.n_images > 64) return false;
+  if (p.precision != 0 && p.precision != 1) return false;
+  if (p.edge_factor < 0 || p.edge_factor > 64) return false;
+  return true;
+}
+
+using TableKey = std::tuple<int, int, int, double>;  // L, periodic, n_images, D
+
+struct Layout {
+  // per distinct lattice
+  std::map<TableKey, int> table_index;
+  std::vector<TableKey> tables;
+  std::vector<int64_t> table_K;
+  std::vector<size_t> off_hd, off_J, off_C, off_guide;
+  // per chain
+  std::vector<int> chain_table;
+  std::vector<int64_t> vbase;
+  std::vector<size_t> off_theta, off_delta, off_delta32;
+  size_t off_sync = 0, off_cd = 0, off_st = 0, off_chunk = 0, off_srcbase = 0;
+  size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0;
+  size_t off_col = 0, off_attr = 0, off_color = 0, off_rho = 0, off_g0 = 0, off_plist = 0, off_perm = 0;
+  size_t off_hist = 0, off_part = 0, off_obs = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
+  int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
+  uint32_t cap_und = 0;
+  size_t bytes = 0;
+};
+
+int make_layout(const sco_chain_params* p, int n, Layout& lay) {
+  size_t off = 0;
+  auto take = [&](size_t nbytes) {
+    const size_t o = off;
+    off = align_up(off + nbytes);
+    return o;
+  };
+  lay.off_sync = take(sizeof(SyncWords));
+  lay.off_cd = take(sizeof(ChainDesc) * n);
+  lay.off_st = take(sizeof(ChainState) * n);
+  int64_t G = 0, edges = 0;
+  for (int c = 0; c < n; ++c) {
+    const TableKey key{p[c].L, p[c].periodic ? 1 : 0, p[c].periodic ? p[c].n_images : 0, p[c].D};
+    auto it = lay.table_index.find(key);
+    int t;
+    if (it == lay.table_index.end()) {
+      t = static_cast<int>(lay.tables.size());
+      lay.table_index[key] = t;
+      lay.tables.push_back(key);
+      lay.table_K.push_back(halfset_size(p[c].L, p[c].periodic));
+    } else {
+      t = it->second;
+    }
+    lay.chain_table.push_back(t);
+    lay.vbase.push_back(G);
+    const int64_t N = static_cast<int64_t>(p[c].L) * p[c].L;
+    G += (N + SCO_CHUNK - 1) / SCO_CHUNK * SCO_CHUNK;
+    const int ef = p[c].edge_factor ? p[c].edge_factor : 4;
+    edges += N * ef / 2;
+  }
+  if (G >= (1LL << 31) - SCO_CHUNK || edges >= (1LL << 30)) return SCO_EINVAL;
+  lay.G = G;
+  lay.nchunks = G / SCO_CHUNK;
+  lay.cap_und = static_cast<uint32_t>(std::max<int64_t>(edges, 1024));
+  lay.off_chunk = take(sizeof(int32_t) * lay.nchunks);
+  lay.off_srcbase = take(sizeof(int64_t) * n);
+  for (size_t t = 0; t < lay.tables.size(); ++t) {
+    const int64_t K = lay.table_K[t];
+    lay.maxK = std::max(lay.maxK, K);
+    lay.off_hd.push_back(take(sizeof(uint32_t) * K));
+    lay.off_J.push_back(take(sizeof(double) * K));
+    lay.off_C.push_back(take(sizeof(double) * K));
+    lay.off_guide.push_back(take(sizeof(int32_t) * (kNB + 1)));
+  }
+  for (int c = 0; c < n; ++c) {
+    const int64_t K = lay.table_K[lay.chain_table[c]];
+    const bool hard = p[c].kappa == 1.0;
+    lay.off_theta.push_back(hard ? 0 : take(sizeof(double) * K));
+    lay.off_delta.push_back(hard ? 0 : take(sizeof(double) * K));
+    lay.off_delta32.push_back(hard ? 0 : take(sizeof(float) * K));
+  }
+  lay.off_spin = take(G);
+  lay.off_deg = take(sizeof(int32_t) * G);
+  lay.off_row = take(sizeof(int32_t) * (G + 1));
+  lay.off_fill = take(sizeof(int32_t) * G);
+  lay.off_ea = take(sizeof(int32_t) * lay.cap_und);
+  lay.off_eb = take(sizeof(int32_t) * lay.cap_und);
+  lay.off_em = take(sizeof(int32_t) * lay.cap_und);
+  lay.off_col = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
+  lay.off_attr = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
+  lay.off_color = take(sizeof(uint16_t) * G);
+  lay.off_rho = take(sizeof(uint16_t) * G);
+  lay.off_g0 = take(sizeof(int32_t) * G);
+  lay.off_plist = take(sizeof(int32_t) * G);
+  lay.off_perm = take(sizeof(int32_t) * G);
+  const int64_t nh = static_cast<int64_t>(SCO_MAXQ) * lay.nchunks;
+  lay.off_hist = take(sizeof(int32_t) * (nh + 1));
+  lay.ntiles = (std::max<int64_t>(G, nh) + 4095) / 4096 + 2;
+  lay.off_part = take(sizeof(int32_t) * lay.ntiles);
+  lay.off_obs = take(sizeof(unsigned long long) * 2 * n);
+  int maxbits = 0;
+  for (int c = 0; c < n; ++c) maxbits = std::max(maxbits, p[c].L * ((p[c].L + 31) / 32));
+  lay.off_bits = take(sizeof(uint32_t) * maxbits);
+  lay.off_prod = take(sizeof(double) * lay.maxK);
+  lay.off_dpart = take(sizeof(double) * (lay.maxK / 4096 + 2));
+  lay.off_dres = take(sizeof(double) * n);
+  lay.bytes = off;
+  return SCO_OK;
+}
+
+// Half-displacement set: each unordered pair of sites is reached from exactly one
+// (owner, displacement) that passes the owner rule; sorted by (r^2, dy, dx).
+void build_halfset(int L, int periodic, std::vector<uint32_t>& hd) {
+  std::vector<std::pair<int, int>> d;
+  if (periodic) {
+    const int h = L / 2;
+    for (int dy = 0; dy <= h; ++dy)
+      for (int dx = -h + 1; dx <= h; ++dx) {
+        const bool keep = (dy > 0 && dy < h) || dx > 0 || (dy == h && dx == 0);
+        if (keep) d.emplace_back(dx, dy);
+      }
+  } else {
+    for (int dy = 0; dy < L; ++dy)
+      for (int dx = -(L - 1); dx < L; ++dx)
+        if (dy > 0 || dx > 0) d.emplace_back(dx, dy);
+  }
+  std::sort(d.begin(), d.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+    const int64_t ra = static_cast<int64_t>(a.first) * a.first + static_cast<int64_t>(a.second) * a.second;
+    const int64_t rb = static_cast<int64_t>(b.first) * b.first + static_cast<int64_t>(b.second) * b.second;
+    if (ra != rb) return ra < rb;
+    if (a.second != b.second) return a.second < b.second;
+    return a.first < b.first;
+  });
+  hd.resize(d.size());
+  for (size_t m = 0; m < d.size(); ++m)
+    hd[m] = static_cast<uint32_t>(static_cast<uint16_t>(d[m].first)) |
+            (static_cast<uint32_t>(static_cast<uint16_t>(d[m].second)) << 16);
+}
+
+}  // namespace
+
+struct sco_ctx {
+  hipStream_t stream = nullptr;
+  int n = 0;
+  std::vector<sco_chain_params> params;
+  Layout lay;
+  char* ws = nullptr;
+  std::vector<std::vector<double>> J, C;          // per table (host copies)
+  std::vector<std::vector<uint32_t>> hd;           // per table
+  std::vector<std::vector<double>> theta, delta;   // per chain (empty when hard)
+  std::vector<ChainDesc> cd;                       // host copy of the descriptors
+  StepArgs args{};
+  int blocks = 0;
+  int nsw_max = 0;
+  unsigned long long* pinned = nullptr;            // read-back staging
+  size_t pinned_bytes = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  float phase_ms[3] = {0, 0, 0};
+  int64_t flags_seen = 0;
+  int last_err = 0;
+};
+
+namespace {
+
+template <typename T>
+T* at(sco_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+#define HIP_TRY(expr)                     \
+  do {                                    \
+    if ((expr) != hipSuccess) return SCO_EHIP; \
+  } while (0)
+
+int read_flags(sco_ctx* c, uint32_t* flags) {
+  HIP_TRY(hipMemcpyAsync(c->pinned, at<SyncWords>(c, c->lay.off_sync), sizeof(SyncWords),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const SyncWords* s = reinterpret_cast<const SyncWords*>(c->pinned);
+  *flags = s->flags;
+  return SCO_OK;
+}
+
+// Clears the flags and the barrier words (a timed-out barrier can leave the count
+// non-zero); returns the code that the flags map to.
+int consume_flags(sco_ctx* c) {
+  uint32_t f = 0;
+  int rc = read_flags(c, &f);
+  if (rc) return rc;
+  if (f == 0) return SCO_OK;
+  c->flags_seen |= f;
+  HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, sizeof(SyncWords), c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (f & SCO_FLAG_TIMEOUT) return SCO_EINTERNAL;
+  if (f & SCO_FLAG_PALETTE) return SCO_EINTERNAL;
+  if (f & SCO_FLAG_OVERFLOW) return SCO_EOVERFLOW;
+  return SCO_EINTERNAL;
+}
+
+int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
+  if (step > 0xFFFFFFFFull) return SCO_EINVAL;
+  c->args.step = static_cast<uint32_t>(step);
+  c->args.nsw_override = nsw_override;
+  c->args.nsw_max = nsw_override >= 0 ? nsw_override : c->nsw_max;
+  HIP_TRY(sco_dev::step(c->stream, c->args, phases, c->blocks));
+  return SCO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sco_strerror(int code) {
+  switch (code) {
+    case SCO_OK: return "ok";
+    case SCO_EINVAL: return "invalid argument";
+    case SCO_EHIP: return "HIP runtime error";
+    case SCO_EOVERFLOW: return "surviving bonds exceeded the edge capacity";
+    case SCO_EINTERNAL: return "internal invariant failed or device wait timed out";
+    case SCO_ENOSPC: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* bytes) {
+  if (!params || n_chains <= 0 || !bytes) return SCO_EINVAL;
+  for (int c = 0; c < n_chains; ++c)
+    if (!valid(params[c])) return SCO_EINVAL;
+  Layout lay;
+  const int rc = make_layout(params, n_chains, lay);
+  if (rc) return rc;
+  *bytes = lay.bytes;
+  return SCO_OK;
+}
+
+int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
+             size_t workspace_bytes, const int8_t* dev_init_spins, void* stream) {
+  if (!out || !params || n_chains <= 0 || !dev_workspace) return SCO_EINVAL;
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) return SCO_EINVAL;
+  for (int c = 0; c < n_chains; ++c)
+    if (!valid(params[c])) return SCO_EINVAL;
+  sco_ctx* c = new (std::nothrow) sco_ctx();
+  if (!c) return SCO_EINTERNAL;
+  int rc = make_layout(params, n_chains, c->lay);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  if (workspace_bytes < c->lay.bytes) {
+    delete c;
+    return SCO_ENOSPC;
+  }
+  c->stream = static_cast<hipStream_t>(stream);
+  c->n = n_chains;
+  c->params.assign(params, params + n_chains);
+  c->ws = static_cast<char*>(dev_workspace);
+  const Layout& L = c->lay;
+  auto fail = [&](int code) {
+    sco_destroy(c);
+    return code;
+  };
+  c->pinned_bytes = std::max<size_t>(4096, sizeof(ChainState) * n_chains + 64);
+  c->pinned_bytes = std::max(c->pinned_bytes, sizeof(unsigned long long) * 2 * n_chains + sizeof(double) * n_chains);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes, hipHostMallocDefault) != hipSuccess)
+    return fail(SCO_EHIP);
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(SCO_EHIP);
+  if (hipMemsetAsync(at<char>(c, L.off_sync), 0, sizeof(SyncWords), c->stream) != hipSuccess) return fail(SCO_EHIP);
+  if (hipMemsetAsync(at<char>(c, L.off_st), 0, sizeof(ChainState) * n_chains, c->stream) != hipSuccess)
+    return fail(SCO_EHIP);
+
+  // displacement tables per lattice: J(d) on the GPU, cumulative sums and the guide on
+  // the host (sequential FP64 sum in table order)
+  const size_t nt = L.tables.size();
+  c->hd.resize(nt);
+  c->J.resize(nt);
+  c->C.resize(nt);
+  for (size_t t = 0; t < nt; ++t) {
+    const int Lt = std::get<0>(L.tables[t]), per = std::get<1>(L.tables[t]);
+    const int nim = std::get<2>(L.tables[t]);
+    const double D = std::get<3>(L.tables[t]);
+    build_halfset(Lt, per, c->hd[t]);
+    const int64_t K = static_cast<int64_t>(c->hd[t].size());
+    if (K != L.table_K[t]) return fail(SCO_EINTERNAL);
+    uint32_t* d_hd = at<uint32_t>(c, L.off_hd[t]);
+    double* d_J = at<double>(c, L.off_J[t]);
+    if (hipMemcpyAsync(d_hd, c->hd[t].data(), sizeof(uint32_t) * K, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return fail(SCO_EHIP);
+    if (sco_dev::table_j(c->stream, d_hd, static_cast<int>(K), Lt, per, nim, D, d_J) != hipSuccess)
+      return fail(SCO_EHIP);
+    c->J[t].resize(K);
+    if (hipMemcpyAsync(c->J[t].data(), d_J, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return fail(SCO_EHIP);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
+    c->C[t].resize(K);
+    double acc = 0.0;
+    for (int64_t m = 0; m < K; ++m) {
+      acc += c->J[t][m];
+      c->C[t][m] = acc;
+    }
+    const double Ctop = c->C[t][K - 1];
+    const double stepb = Ctop / kNB;
+    std::vector<int32_t> guide(kNB + 1);
+    for (int b = 0; b <= kNB; ++b) {
+      const double thr = static_cast<double>(b) * stepb;
+      const auto it = std::lower_bound(c->C[t].begin(), c->C[t].end(), thr);
+      guide[b] = it == c->C[t].end() ? static_cast<int32_t>(K - 1) : static_cast<int32_t>(it - c->C[t].begin());
+    }
+    if (hipMemcpyAsync(at<double>(c, L.off_C[t]), c->C[t].data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(at<int32_t>(c, L.off_guide[t]), guide.data(), sizeof(int32_t) * (kNB + 1),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return fail(SCO_EHIP);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
+  }
+
+  // per-chain switching and pseudo-interaction columns (Eqs. 2-3) and descriptors
+  c->theta.resize(n_chains);
+  c->delta.resize(n_chains);
+  c->cd.resize(n_chains);
+  std::vector<int32_t> chunk_chain(L.nchunks, 0);
+  std::vector<int64_t> src_base(n_chains, 0);
+  int64_t sb = 0;
+  for (int ci = 0; ci < n_chains; ++ci) {
+    const sco_chain_params& p = params[ci];
+    const int t = L.chain_table[ci];
+    const int64_t K = L.table_K[t];
+    const double beta = 1.0 / p.T;
+    const bool hard = p.kappa == 1.0;
+    ChainDesc d{};
+    d.L = p.L;
+    d.N = p.L * p.L;
+    d.K = static_cast<int32_t>(K);
+    d.periodic = p.periodic ? 1 : 0;
+    d.vbase = L.vbase[ci];
+    d.hd = at<uint32_t>(c, L.off_hd[t]);
+    d.J = at<double>(c, L.off_J[t]);
+    d.C = at<double>(c, L.off_C[t]);
+    d.guide = at<int32_t>(c, L.off_guide[t]);
+    d.C_top = c->C[t][K - 1];
+    d.guide_inv = static_cast<double>(kNB) / d.C_top;
+    d.nguide = kNB;
+    d.twoJ = 2.0 * p.J;
+    d.beta = beta;
+    d.neg_beta = -beta;
+    d.inv_rate = p.T / (p.kappa + 1.0);
+    for (int k = -4; k <= 4; ++k) {
+      const double dE = (2.0 * p.J) * static_cast<double>(k);
+      d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
+    }
+    d.seed = p.seed;
+    d.chain_id = p.chain_id;
+    d.hard = hard ? 1 : 0;
+    d.precision = p.precision;
+    d.n_sw = p.n_sw;
+    if (!hard) {
+      std::vector<double>& th = c->theta[ci];
+      std::vector<double>& de = c->delta[ci];
+      std::vector<float> de32(K);
+      th.resize(K);
+      de.resize(K);
+      const std::vector<double>& Jt = c->J[t];
+      for (int64_t m = 0; m < K; ++m) {
+        const double em = std::expm1(-beta * (p.kappa + 1.0) * Jt[m]);
+        const double ep = std::expm1(-beta * (p.kappa - 1.0) * Jt[m]);
+        th[m] = ep / em;
+        de[m] = 2.0 * Jt[m] + p.T * std::log(em / ep);
+        de32[m] = static_cast<float>(de[m]);
+      }
+      d.theta = at<double>(c, L.off_theta[ci]);
+      d.delta = at<double>(c, L.off_delta[ci]);
+      d.delta32 = at<float>(c, L.off_delta32[ci]);
+      if (hipMemcpyAsync(const_cast<double*>(d.theta), th.data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess ||
+          hipMemcpyAsync(const_cast<double*>(d.delta), de.data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess ||
+          hipMemcpyAsync(const_cast<float*>(d.delta32), de32.data(), sizeof(float) * K, hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess)
+        return fail(SCO_EHIP);
+      if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
+    }
+    c->cd[ci] = d;
+    const int64_t ch0 = L.vbase[ci] / SCO_CHUNK, chn = (static_cast<int64_t>(d.N) + SCO_CHUNK - 1) / SCO_CHUNK;
+    for (int64_t ch = ch0; ch < ch0 + chn; ++ch) chunk_chain[ch] = ci;
+    src_base[ci] = sb;
+    sb += d.N;
+    c->nsw_max = std::max(c->nsw_max, p.n_sw);
+  }
+  if (hipMemcpyAsync(at<ChainDesc>(c, L.off_cd), c->cd.data(), sizeof(ChainDesc) * n_chains, hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(at<int32_t>(c, L.off_chunk), chunk_chain.data(), sizeof(int32_t) * L.nchunks,
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(at<int64_t>(c, L.off_srcbase), src_base.data(), sizeof(int64_t) * n_chains,
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return fail(SCO_EHIP);
+  if (sco_dev::init_spins(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
+                          at<int64_t>(c, L.off_srcbase), dev_init_spins, at<int8_t>(c, L.off_spin), L.G) != hipSuccess)
+    return fail(SCO_EHIP);
+  // the row offsets start empty so that sco_color / sco_sweep before any switching
+  // see an empty bond graph
+  if (hipMemsetAsync(at<int32_t>(c, L.off_row), 0, sizeof(int32_t) * (L.G + 1), c->stream) != hipSuccess)
+    return fail(SCO_EHIP);
+
+  StepArgs& a = c->args;
+  a.cd = at<ChainDesc>(c, L.off_cd);
+  a.st = at<ChainState>(c, L.off_st);
+  a.sync = at<SyncWords>(c, L.off_sync);
+  a.chunk_chain = at<int32_t>(c, L.off_chunk);
+  a.spin = at<int8_t>(c, L.off_spin);
+  a.deg = at<int32_t>(c, L.off_deg);
+  a.row_ptr = at<int32_t>(c, L.off_row);
+  a.fill = at<int32_t>(c, L.off_fill);
+  a.ea = at<int32_t>(c, L.off_ea);
+  a.eb = at<int32_t>(c, L.off_eb);
+  a.em = at<int32_t>(c, L.off_em);
+  a.col = at<int32_t>(c, L.off_col);
+  a.attr = at<int32_t>(c, L.off_attr);
+  a.color = at<uint16_t>(c, L.off_color);
+  a.rho = at<uint16_t>(c, L.off_rho);
+  a.g0 = at<int32_t>(c, L.off_g0);
+  a.plist = at<int32_t>(c, L.off_plist);
+  a.perm = at<int32_t>(c, L.off_perm);
+  a.hist = at<int32_t>(c, L.off_hist);
+  a.part = at<int32_t>(c, L.off_part);
+  a.G = L.G;
+  a.nchunks = static_cast<int32_t>(L.nchunks);
+  a.n_chains = n_chains;
+  a.cap_und = L.cap_und;
+  const int maxb = sco_dev::step_max_blocks();
+  if (maxb <= 0) return fail(SCO_EHIP);
+  c->blocks = static_cast<int>(std::min<int64_t>(maxb, std::max<int64_t>(1, L.nchunks)));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
+  *out = c;
+  return SCO_OK;
+}
+
+int sco_switch(sco_ctx* c, uint64_t step) {
+  if (!c) return SCO_EINVAL;
+  HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  int rc = launch(c, PH_SWITCH, step, 0);
+  HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+  return rc;
+}
+
+int sco_color(sco_ctx* c) {
+  if (!c) return SCO_EINVAL;
+  HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+  int rc = launch(c, PH_COLOR, 0, 0);
+  HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+  return rc;
+}
+
+int sco_sweep(sco_ctx* c, uint64_t step, int n_sw) {
+  if (!c || n_sw < 0) return SCO_EINVAL;
+  HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+  int rc = launch(c, PH_SWEEP, step, n_sw);
+  HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+  return rc;
+}
+
+int sco_step(sco_ctx* c, uint64_t step) {
+  if (!c) return SCO_EINVAL;
+  return launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, step, -1);
+}
+
+int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
+  if (!c || n_steps < 0) return SCO_EINVAL;
+  for (int s = 0; s < n_steps; ++s) {
+    const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, first_step + static_cast<uint64_t>(s), -1);
+    if (rc) return rc;
+  }
+  return SCO_OK;
+}
+
+int sco_phase_times(sco_ctx* c, float* out3) {
+  if (!c || !out3) return SCO_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 3; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) != hipSuccess) ms = -1.f;
+    out3[i] = ms;
+  }
+  return SCO_OK;
+}
+
+int sco_reset_counters(sco_ctx* c) {
+  if (!c) return SCO_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<ChainState> st(c->n);
+  HIP_TRY(hipMemcpy(st.data(), at<ChainState>(c, c->lay.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost));
+  for (auto& s : st) s.accepted = s.attempts = s.rechecks = s.near_ties = 0;
+  HIP_TRY(hipMemcpy(at<ChainState>(c, c->lay.off_st), st.data(), sizeof(ChainState) * c->n, hipMemcpyHostToDevice));
+  c->flags_seen = 0;
+  return SCO_OK;
+}
+
+int sco_observables(sco_ctx* c, sco_obs* out) {
+  if (!c || !out) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  const Layout& L = c->lay;
+  unsigned long long* d_obs = at<unsigned long long>(c, L.off_obs);
+  HIP_TRY(hipMemsetAsync(d_obs, 0, sizeof(unsigned long long) * 2 * c->n, c->stream));
+  HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
+                             at<int8_t>(c, L.off_spin), d_obs, L.G));
+  for (int ci = 0; ci < c->n; ++ci) {
+    const ChainDesc& d = c->cd[ci];
+    const int t = L.chain_table[ci];
+    HIP_TRY(sco_dev::obs_dipolar(c->stream, d.hd, d.J, d.K, d.L, d.periodic, at<int8_t>(c, L.off_spin), d.vbase,
+                                 at<uint32_t>(c, L.off_bits), at<double>(c, L.off_prod), at<double>(c, L.off_dpart),
+                                 at<double>(c, L.off_dres) + ci));
+    (void)t;
+  }
+  std::vector<ChainState> st(c->n);
+  std::vector<unsigned long long> sums(2 * c->n);
+  std::vector<double> edip(c->n);
+  HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(sums.data(), d_obs, sizeof(unsigned long long) * 2 * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(edip.data(), at<double>(c, L.off_dres), sizeof(double) * c->n, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int ci = 0; ci < c->n; ++ci) {
+    sco_obs& o = out[ci];
+    const ChainState& s = st[ci];
+    o.M = static_cast<long long>(sums[2 * ci]);
+    o.E_exchange = -c->params[ci].J * static_cast<double>(static_cast<long long>(sums[2 * ci + 1]));
+    o.E_dipolar = edip[ci];
+    o.E = o.E_exchange + o.E_dipolar;
+    o.n_edges = s.n_edges / 2;
+    o.delta_union = s.delta_union;
+    o.q = s.q;
+    o.colors_used = s.colors_used;
+    o.kw_levels = s.M;
+    int64_t r = 0;
+    for (int p = 0; p < SCO_MAXLEVEL; ++p) r += s.kw_rounds[p];
+    o.kw_rounds = r;
+    o.accepted = static_cast<int64_t>(s.accepted);
+    o.attempts = static_cast<int64_t>(s.attempts);
+    o.rechecks = static_cast<int64_t>(s.rechecks);
+    o.flags = c->flags_seen;
+  }
+  return fr;
+}
+
+int sco_get_spins(sco_ctx* c, int chain, int8_t* host_out) {
+  if (!c || chain < 0 || chain >= c->n || !host_out) return SCO_EINVAL;
+  const ChainDesc& d = c->cd[chain];
+  HIP_TRY(hipMemcpyAsync(host_out, at<int8_t>(c, c->lay.off_spin) + d.vbase, d.N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+int sco_set_spins(sco_ctx* c, int chain, const int8_t* host_in) {
+  if (!c || chain < 0 || chain >= c->n || !host_in) return SCO_EINVAL;
+  const ChainDesc& d = c->cd[chain];
+  std::vector<int8_t> s(d.N);
+  for (int v = 0; v < d.N; ++v) s[v] = host_in[v] > 0 ? 1 : -1;
+  HIP_TRY(hipMemcpyAsync(at<int8_t>(c, c->lay.off_spin) + d.vbase, s.data(), d.N, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+int sco_get_graph(sco_ctx* c, int chain, int32_t* row_ptr, int32_t* col, int32_t* attr, int32_t* colors,
+                  int64_t* n_dir) {
+  if (!c || chain < 0 || chain >= c->n) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  const ChainDesc& d = c->cd[chain];
+  const Layout& L = c->lay;
+  std::vector<int32_t> rp(d.N + 1);
+  HIP_TRY(hipMemcpyAsync(rp.data(), at<int32_t>(c, L.off_row) + d.vbase, sizeof(int32_t) * (d.N + 1),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int32_t e0 = rp[0], e1 = rp[d.N];
+  if (n_dir) *n_dir = e1 - e0;
+  if (row_ptr)
+    for (int v = 0; v <= d.N; ++v) row_ptr[v] = rp[v] - e0;
+  if ((col || attr) && e1 > e0) {
+    std::vector<int32_t> cl(e1 - e0);
+    HIP_TRY(hipMemcpy(cl.data(), at<int32_t>(c, L.off_col) + e0, sizeof(int32_t) * (e1 - e0), hipMemcpyDeviceToHost));
+    if (col)
+      for (int32_t i = 0; i < e1 - e0; ++i) col[i] = cl[i] - static_cast<int32_t>(d.vbase);
+    if (attr)
+      HIP_TRY(hipMemcpy(attr, at<int32_t>(c, L.off_attr) + e0, sizeof(int32_t) * (e1 - e0), hipMemcpyDeviceToHost));
+  }
+  if (colors) {
+    std::vector<uint16_t> cc(d.N);
+    HIP_TRY(hipMemcpy(cc.data(), at<uint16_t>(c, L.off_color) + d.vbase, sizeof(uint16_t) * d.N,
+                      hipMemcpyDeviceToHost));
+    for (int v = 0; v < d.N; ++v) colors[v] = cc[v];
+  }
+  return fr;
+}
+
+int sco_get_tables(sco_ctx* c, int chain, int32_t* K, int32_t* dx, int32_t* dy, double* J, double* C,
+                   double* theta, double* delta) {
+  if (!c || chain < 0 || chain >= c->n) return SCO_EINVAL;
+  const int t = c->lay.chain_table[chain];
+  const int64_t n = c->lay.table_K[t];
+  if (K) *K = static_cast<int32_t>(n);
+  for (int64_t m = 0; m < n; ++m) {
+    const uint32_t p = c->hd[t][m];
+    if (dx) dx[m] = static_cast<int16_t>(p & 0xFFFFu);
+    if (dy) dy[m] = static_cast<int16_t>(p >> 16);
+    if (J) J[m] = c->J[t][m];
+    if (C) C[m] = c->C[t][m];
+    if (theta) theta[m] = c->theta[chain].empty() ? 0.0 : c->theta[chain][m];
+    if (delta) delta[m] = c->delta[chain].empty() ? INFINITY : c->delta[chain][m];
+  }
+  return SCO_OK;
+}
+
+int sco_destroy(sco_ctx* c) {
+  if (!c) return SCO_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+  return SCO_OK;
+}
+
+}  // extern "C"

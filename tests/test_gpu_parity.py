@@ -1,0 +1,123 @@
+"""HIP path vs the CPU reference, element by element, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.parity import compare_observables, gpu_params, log, oracle_params, run_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1503_03295_amd import lib
+
+    lib()
+    yield
+
+
+@pytest.mark.parametrize("L,periodic,kappa,T", [(32, False, 1.0, 1.0), (32, False, 2.0, 1.0),
+                                                (64, True, 1.5, 0.8), (256, True, 1.0, 1.2),
+                                                (6, True, 2.0, 2.0), (2, False, 1.0, 1.0)])
+def test_tables_bit_exact(L, periodic, kappa, T):
+    from paper_1503_03295_amd import SCO
+
+    log(f"tables L={L} periodic={periodic} kappa={kappa}")
+    p = workloads.chain(L, periodic, T, kappa)
+    gpu = SCO([gpu_params(p)], device="cuda:0")
+    ref = oracle.OracleChain(oracle_params(p))
+    g, r = gpu.tables(0), ref.tables()
+    for k in ("dx", "dy", "J", "C", "theta", "delta"):
+        np.testing.assert_array_equal(g[k], r[k], err_msg=k)
+    np.testing.assert_array_equal(gpu.spins(0), ref.spins)
+
+
+@pytest.mark.parametrize("kappa", [1.0, 2.0])
+def test_small_open_lattice_full_run(kappa):
+    """L=32 open, T=1.0: every step of a 1000-step run (spins, CSR, colours)."""
+    params, n_steps = workloads.small_open(kappa)
+    log(f"small open kappa={kappa}")
+    out = run_parity(params, n_steps, graph_every=1, obs_every=100)
+    log(f"  tolerated near ties: {out['tolerated']}")
+
+
+@pytest.mark.parametrize("kappa", [1.0, 2.0])
+def test_medium_periodic_three_temperatures(kappa):
+    """L=256 periodic, T in {0.8, 1.2, 2.0}, three chains in one context."""
+    params, _ = workloads.medium_periodic(kappa)
+    log(f"medium periodic kappa={kappa}")
+    out = run_parity(params, 40, graph_every=5, obs_every=20)
+    log(f"  tolerated near ties: {out['tolerated']}")
+
+
+def test_ragged_batch_of_chains():
+    """Chains of different L, boundaries, kappa and n_sw in one launch."""
+    params = [workloads.chain(8, True, 2.0, 2.0, chain_id=0, n_sw=2),
+              workloads.chain(33, False, 1.1, 1.0, chain_id=1),
+              workloads.chain(64, True, 0.9, 1.0, chain_id=2, n_sw=3),
+              workloads.chain(20, False, 1.7, 3.0, chain_id=3, n_sw=0),
+              workloads.chain(48, True, 1.3, 2.0, chain_id=4, seed=7)]
+    log("ragged batch")
+    run_parity(params, 30, graph_every=3, obs_every=10)
+
+
+def test_split_entry_points_equal_step():
+    """sco_switch + sco_color + sco_sweep == sco_step."""
+    from paper_1503_03295_amd import SCO
+
+    p = workloads.chain(64, True, 1.0, 2.0, n_sw=2)
+    a = SCO([gpu_params(p)], device="cuda:0")
+    b = SCO([gpu_params(p)], device="cuda:0")
+    for t in range(5):
+        a.step(t)
+        b.switch(t)
+        b.color()
+        b.sweep(t, 2)
+    np.testing.assert_array_equal(a.spins(0), b.spins(0))
+
+
+def test_checkpoint_resume_exact():
+    from paper_1503_03295_amd import SCO
+
+    p = workloads.chain(128, True, 1.2, 2.0)
+    a = SCO([gpu_params(p)], device="cuda:0")
+    for t in range(6):
+        a.step(t)
+        if t == 2:
+            saved = a.spins(0)
+    b = SCO([gpu_params(p)], device="cuda:0")
+    b.set_spins(0, saved)
+    for t in range(3, 6):
+        b.step(t)
+    np.testing.assert_array_equal(a.spins(0), b.spins(0))
+
+
+def test_edge_capacity_overflow_is_reported():
+    from paper_1503_03295_amd import SCO, ScoError
+
+    p = workloads.chain(64, True, 0.8, 3.0)
+    p["edge_factor"] = 1
+    g = SCO([gpu_params(p)], device="cuda:0")
+    g.step(0)
+    with pytest.raises(ScoError) as e:
+        g.observables()
+    assert e.value.code == -3
+    # the context stays usable after the flag was consumed
+    g.observables()
+
+
+def test_large_lattice_first_steps():
+    """L=2304 periodic (N = 5.3M), T=1.2: full parity of the first two steps."""
+    params, _ = workloads.large_periodic()
+    log("L=2304 two steps")
+    out = run_parity(params, 2, graph_every=1, obs_every=0)
+    gpu, refs = out["gpu"], out["refs"]
+    go = gpu.observables()[0]
+    ro = refs[0].observables(dipolar="fft")
+    for k in ("M", "n_edges", "delta_union", "q", "colors_used", "kw_levels", "kw_rounds"):
+        assert go[k] == ro[k], k
+    assert abs(go["E"] - ro["E"]) <= 1e-12 * abs(ro["E"])
