@@ -63,7 +63,7 @@ typedef struct {
   uint32_t seed;      /* Philox key word 0 */
   uint32_t chain_id;  /* Philox key word 1 */
   int32_t precision;  /* 0: FP64 decisions; 1: FP32 accumulation + FP64 recheck (same chain) */
-  int32_t edge_factor;/* directed-bond capacity per site (0: default 8) */
+  int32_t edge_factor;/* directed-bond capacity per site (0: default 4) */
 } sco_chain_params;
 
 /* Per-chain observables and counters, FP64 / exact integers. */
@@ -81,7 +81,9 @@ typedef struct {
   int64_t accepted;   /* accepted flips since sco_init (or the last counter reset) */
   int64_t attempts;   /* Metropolis trials since sco_init */
   int64_t rechecks;   /* FP32 decisions recomputed in FP64 (precision 1) */
-  int64_t flags;      /* device flags seen (bit 0 overflow, bit 1 wait timeout) */
+  int64_t flags;      /* device flags seen since the last counter reset: bit 0 edge
+                         overflow, bit 1 wait timeout, bit 2 palette overflow,
+                         bit 3 colouring or sweep launched without a valid graph */
 } sco_obs;
 
 typedef struct sco_ctx sco_ctx;
@@ -137,6 +139,15 @@ int sco_get_tables(sco_ctx* ctx, int chain, int32_t* K, int32_t* dx, int32_t* dy
 /* Device time of the phases of the last sco_step/sco_run call, in ms:
  * out[0] switching + assembly, out[1] colouring, out[2] sweeps (events on the stream). */
 int sco_phase_times(sco_ctx* ctx, float* out3);
+
+/* Phase trace of the persistent step kernel: while enabled, block 0 records a mark
+ * (an id and the wall clock) at each phase boundary of every launch.  sco_trace_read
+ * returns the marks of the last launch (ids, microseconds since its first mark) and
+ * their count in *n; it synchronises.  Ids: 1-6 switching (draws, scan, scatter,
+ * row sort), 10-13 colouring (tile levels, 100+p global level p), 20-22 sweeps
+ * (1000+k colour class k).  Diagnostic only; costs a small copy per launch. */
+int sco_trace(sco_ctx* ctx, int enable);
+int sco_trace_read(sco_ctx* ctx, int32_t* ids, double* us, int max, int* n);
 
 /* Sets counters (accepted, attempts, rechecks, flags) of every chain to zero. */
 int sco_reset_counters(sco_ctx* ctx);

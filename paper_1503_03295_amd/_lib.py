@@ -12,7 +12,8 @@ SCO_OK, SCO_EINVAL, SCO_EHIP, SCO_EOVERFLOW, SCO_EINTERNAL, SCO_ENOSPC = 0, -1, 
 EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
-    "sco_phase_times", "sco_reset_counters", "sco_destroy", "sco_strerror",
+    "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
+    "sco_strerror",
 ]
 
 
@@ -75,6 +76,8 @@ def lib():
         "sco_get_graph": ([P, i32, P, P, P, P, ctypes.POINTER(ctypes.c_int64)], i32),
         "sco_get_tables": ([P, i32, ctypes.POINTER(ctypes.c_int32), P, P, P, P, P, P], i32),
         "sco_phase_times": ([P, ctypes.POINTER(ctypes.c_float)], i32),
+        "sco_trace": ([P, i32], i32),
+        "sco_trace_read": ([P, P, P, i32, ctypes.POINTER(ctypes.c_int)], i32),
         "sco_reset_counters": ([P], i32),
         "sco_destroy": ([P], i32),
         "sco_strerror": ([i32], ctypes.c_char_p),

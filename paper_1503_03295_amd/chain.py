@@ -149,5 +149,18 @@ class SCO:
         check(lib().sco_phase_times(self._h, out), "sco_phase_times")
         return tuple(out)
 
+    def trace(self, enable: bool = True) -> None:
+        check(lib().sco_trace(self._h, int(enable)), "sco_trace")
+
+    def trace_read(self) -> list[tuple[int, float]]:
+        n = ctypes.c_int(0)
+        ids = np.zeros(256, np.int32)
+        us = np.zeros(256)
+        check(lib().sco_trace_read(self._h, ids.ctypes.data_as(ctypes.c_void_p),
+                                   us.ctypes.data_as(ctypes.c_void_p), 256, ctypes.byref(n)),
+              "sco_trace_read")
+        k = min(n.value, 256)
+        return list(zip(ids[:k].tolist(), us[:k].tolist()))
+
     def reset_counters(self) -> None:
         check(lib().sco_reset_counters(self._h), "sco_reset_counters")

@@ -50,8 +50,8 @@ struct Layout {
   std::vector<size_t> off_theta, off_delta, off_delta32;
   size_t off_sync = 0, off_cd = 0, off_st = 0, off_chunk = 0, off_srcbase = 0;
   size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0;
-  size_t off_col = 0, off_attr = 0, off_color = 0, off_rho = 0, off_g0 = 0, off_plist = 0, off_perm = 0;
-  size_t off_hist = 0, off_part = 0, off_obs = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
+  size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_plist = 0, off_ecount = 0, off_trace = 0;
+  size_t off_ts = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -85,12 +85,13 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
     const int64_t N = static_cast<int64_t>(p[c].L) * p[c].L;
     G += (N + SCO_CHUNK - 1) / SCO_CHUNK * SCO_CHUNK;
     const int ef = p[c].edge_factor ? p[c].edge_factor : 4;
-    edges += N * ef / 2;
+    edges = std::max<int64_t>(edges, static_cast<int64_t>(SCO_CHUNK) * ef / 2);  // per chunk
   }
-  if (G >= (1LL << 31) - SCO_CHUNK || edges >= (1LL << 30)) return SCO_EINVAL;
   lay.G = G;
   lay.nchunks = G / SCO_CHUNK;
-  lay.cap_und = static_cast<uint32_t>(std::max<int64_t>(edges, 1024));
+  // every chunk gets the same survivor region: the largest edge factor of the chains
+  if (G >= (1LL << 31) - SCO_CHUNK || edges * lay.nchunks >= (1LL << 30)) return SCO_EINVAL;
+  lay.cap_und = static_cast<uint32_t>(edges * lay.nchunks);
   lay.off_chunk = take(sizeof(int32_t) * lay.nchunks);
   lay.off_srcbase = take(sizeof(int64_t) * n);
   for (size_t t = 0; t < lay.tables.size(); ++t) {
@@ -118,15 +119,14 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_col = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
   lay.off_attr = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
   lay.off_color = take(sizeof(uint16_t) * G);
-  lay.off_rho = take(sizeof(uint16_t) * G);
-  lay.off_g0 = take(sizeof(int32_t) * G);
+  lay.off_word = take(sizeof(uint32_t) * G);
   lay.off_plist = take(sizeof(int32_t) * G);
-  lay.off_perm = take(sizeof(int32_t) * G);
-  const int64_t nh = static_cast<int64_t>(SCO_MAXQ) * lay.nchunks;
-  lay.off_hist = take(sizeof(int32_t) * (nh + 1));
-  lay.ntiles = (std::max<int64_t>(G, nh) + 4095) / 4096 + 2;
-  lay.off_part = take(sizeof(int32_t) * lay.ntiles);
+  lay.off_ecount = take(sizeof(uint32_t) * lay.nchunks);
+  lay.off_trace = take(sizeof(unsigned long long) * SCO_TRACE_SLOTS);
+  lay.ntiles = G / (16 * SCO_CHUNK) + 2;
+  lay.off_ts = take(sizeof(unsigned long long) * lay.ntiles);
   lay.off_obs = take(sizeof(unsigned long long) * 2 * n);
+  lay.off_used = take(sizeof(uint32_t) * (SCO_MAXQ / 32) * n);
   int maxbits = 0;
   for (int c = 0; c < n; ++c) maxbits = std::max(maxbits, p[c].L * ((p[c].L + 31) / 32));
   lay.off_bits = take(sizeof(uint32_t) * maxbits);
@@ -181,6 +181,10 @@ struct sco_ctx {
   StepArgs args{};
   int blocks = 0;
   int nsw_max = 0;
+  int graph_state = 0;  // 0 no bond graph yet, 1 switched, 2 switched and coloured
+  uint32_t epoch = 0;
+  bool trace_on = false;
+  double wall_mhz = 100.0;
   unsigned long long* pinned = nullptr;            // read-back staging
   size_t pinned_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -202,11 +206,10 @@ T* at(sco_ctx* c, size_t off) {
   } while (0)
 
 int read_flags(sco_ctx* c, uint32_t* flags) {
-  HIP_TRY(hipMemcpyAsync(c->pinned, at<SyncWords>(c, c->lay.off_sync), sizeof(SyncWords),
-                         hipMemcpyDeviceToHost, c->stream));
+  const SyncWords* d = at<SyncWords>(c, c->lay.off_sync);
+  HIP_TRY(hipMemcpyAsync(c->pinned, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  const SyncWords* s = reinterpret_cast<const SyncWords*>(c->pinned);
-  *flags = s->flags;
+  *flags = *reinterpret_cast<const uint32_t*>(c->pinned);
   return SCO_OK;
 }
 
@@ -218,6 +221,9 @@ int consume_flags(sco_ctx* c) {
   if (rc) return rc;
   if (f == 0) return SCO_OK;
   c->flags_seen |= f;
+  // a flagged launch may have stopped part-way: the bond graph and colouring are not
+  // valid any more (the device words are cleared with the rest of the sync block)
+  c->graph_state = 0;
   HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, sizeof(SyncWords), c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (f & SCO_FLAG_TIMEOUT) return SCO_EINTERNAL;
@@ -229,6 +235,14 @@ int consume_flags(sco_ctx* c) {
 int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
   if (step > 0xFFFFFFFFull) return SCO_EINVAL;
   c->args.step = static_cast<uint32_t>(step);
+  c->args.epoch = ++c->epoch & 0xFFFFFFu;
+  if (c->args.epoch == 0xFFFFFFu) c->args.epoch = c->epoch = 1;
+  if (c->trace_on) {
+    c->args.trace = at<unsigned long long>(c, c->lay.off_trace);
+    HIP_TRY(hipMemsetAsync(c->args.trace, 0, sizeof(unsigned long long), c->stream));
+  } else {
+    c->args.trace = nullptr;
+  }
   c->args.nsw_override = nsw_override;
   c->args.nsw_max = nsw_override >= 0 ? nsw_override : c->nsw_max;
   HIP_TRY(sco_dev::step(c->stream, c->args, phases, c->blocks));
@@ -252,7 +266,7 @@ const char* sco_strerror(int code) {
 }
 
 int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* bytes) {
-  if (!params || n_chains <= 0 || !bytes) return SCO_EINVAL;
+  if (!params || n_chains <= 0 || n_chains > SCO_MAXCHAINS || !bytes) return SCO_EINVAL;
   for (int c = 0; c < n_chains; ++c)
     if (!valid(params[c])) return SCO_EINVAL;
   Layout lay;
@@ -264,7 +278,7 @@ int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* byt
 
 int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
              size_t workspace_bytes, const int8_t* dev_init_spins, void* stream) {
-  if (!out || !params || n_chains <= 0 || !dev_workspace) return SCO_EINVAL;
+  if (!out || !params || n_chains <= 0 || n_chains > SCO_MAXCHAINS || !dev_workspace) return SCO_EINVAL;
   *out = nullptr;
   if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) return SCO_EINVAL;
   for (int c = 0; c < n_chains; ++c)
@@ -373,6 +387,7 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
     d.twoJ = 2.0 * p.J;
     d.beta = beta;
     d.neg_beta = -beta;
+    d.inv_L = 1.0 / p.L;
     d.inv_rate = p.T / (p.kappa + 1.0);
     for (int k = -4; k <= 4; ++k) {
       const double dE = (2.0 * p.J) * static_cast<double>(k);
@@ -426,9 +441,13 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   if (sco_dev::init_spins(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
                           at<int64_t>(c, L.off_srcbase), dev_init_spins, at<int8_t>(c, L.off_spin), L.G) != hipSuccess)
     return fail(SCO_EHIP);
-  // the row offsets start empty so that sco_color / sco_sweep before any switching
-  // see an empty bond graph
-  if (hipMemsetAsync(at<int32_t>(c, L.off_row), 0, sizeof(int32_t) * (L.G + 1), c->stream) != hipSuccess)
+  // degrees and scatter cursors are zero between steps; the scan tile states start
+  // with a tag that no launch uses
+  if (hipMemsetAsync(at<int32_t>(c, L.off_row), 0, sizeof(int32_t) * (L.G + 1), c->stream) != hipSuccess ||
+      hipMemsetAsync(at<int32_t>(c, L.off_deg), 0, sizeof(int32_t) * L.G, c->stream) != hipSuccess ||
+      hipMemsetAsync(at<int32_t>(c, L.off_fill), 0, sizeof(int32_t) * L.G, c->stream) != hipSuccess ||
+      hipMemsetAsync(at<unsigned long long>(c, L.off_ts), 0xFF, sizeof(unsigned long long) * L.ntiles,
+                     c->stream) != hipSuccess)
     return fail(SCO_EHIP);
 
   StepArgs& a = c->args;
@@ -446,19 +465,28 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   a.col = at<int32_t>(c, L.off_col);
   a.attr = at<int32_t>(c, L.off_attr);
   a.color = at<uint16_t>(c, L.off_color);
-  a.rho = at<uint16_t>(c, L.off_rho);
-  a.g0 = at<int32_t>(c, L.off_g0);
+  a.kw_word = at<uint32_t>(c, L.off_word);
   a.plist = at<int32_t>(c, L.off_plist);
-  a.perm = at<int32_t>(c, L.off_perm);
-  a.hist = at<int32_t>(c, L.off_hist);
-  a.part = at<int32_t>(c, L.off_part);
+  a.ecount = at<uint32_t>(c, L.off_ecount);
+  a.trace = nullptr;
+  a.scan_ts = at<unsigned long long>(c, L.off_ts);
   a.G = L.G;
   a.nchunks = static_cast<int32_t>(L.nchunks);
   a.n_chains = n_chains;
   a.cap_und = L.cap_und;
   const int maxb = sco_dev::step_max_blocks();
   if (maxb <= 0) return fail(SCO_EHIP);
-  c->blocks = static_cast<int>(std::min<int64_t>(maxb, std::max<int64_t>(1, L.nchunks)));
+  c->blocks = std::min(maxb, SCO_MAX_BLOCKS);
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      c->wall_mhz = khz / 1000.0;
+  }
+  // colouring words start at level 31, which no colouring reaches (they are all
+  // rewritten by the tile levels of every colouring before any level reads them)
+  if (hipMemsetAsync(at<uint32_t>(c, L.off_word), 0xFF, sizeof(uint32_t) * L.G, c->stream) != hipSuccess)
+    return fail(SCO_EHIP);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
   *out = c;
   return SCO_OK;
@@ -469,19 +497,23 @@ int sco_switch(sco_ctx* c, uint64_t step) {
   HIP_TRY(hipEventRecord(c->ev[0], c->stream));
   int rc = launch(c, PH_SWITCH, step, 0);
   HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+  if (rc == SCO_OK) c->graph_state = 1;
   return rc;
 }
 
 int sco_color(sco_ctx* c) {
   if (!c) return SCO_EINVAL;
+  if (c->graph_state < 1) return SCO_EINVAL;  // no bond graph to colour yet
   HIP_TRY(hipEventRecord(c->ev[1], c->stream));
   int rc = launch(c, PH_COLOR, 0, 0);
   HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+  if (rc == SCO_OK) c->graph_state = 2;
   return rc;
 }
 
 int sco_sweep(sco_ctx* c, uint64_t step, int n_sw) {
   if (!c || n_sw < 0) return SCO_EINVAL;
+  if (c->graph_state != 2) return SCO_EINVAL;  // the colouring must match the bond graph
   HIP_TRY(hipEventRecord(c->ev[2], c->stream));
   int rc = launch(c, PH_SWEEP, step, n_sw);
   HIP_TRY(hipEventRecord(c->ev[3], c->stream));
@@ -490,7 +522,9 @@ int sco_sweep(sco_ctx* c, uint64_t step, int n_sw) {
 
 int sco_step(sco_ctx* c, uint64_t step) {
   if (!c) return SCO_EINVAL;
-  return launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, step, -1);
+  const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, step, -1);
+  if (rc == SCO_OK) c->graph_state = 2;
+  return rc;
 }
 
 int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
@@ -498,6 +532,7 @@ int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
   for (int s = 0; s < n_steps; ++s) {
     const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, first_step + static_cast<uint64_t>(s), -1);
     if (rc) return rc;
+    c->graph_state = 2;
   }
   return SCO_OK;
 }
@@ -509,6 +544,29 @@ int sco_phase_times(sco_ctx* c, float* out3) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) != hipSuccess) ms = -1.f;
     out3[i] = ms;
+  }
+  return SCO_OK;
+}
+
+int sco_trace(sco_ctx* c, int enable) {
+  if (!c) return SCO_EINVAL;
+  c->trace_on = enable != 0;
+  return SCO_OK;
+}
+
+int sco_trace_read(sco_ctx* c, int32_t* ids, double* us, int max, int* n) {
+  if (!c || !n || max < 0) return SCO_EINVAL;
+  std::vector<unsigned long long> t(SCO_TRACE_SLOTS);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(t.data(), at<unsigned long long>(c, c->lay.off_trace), sizeof(unsigned long long) * t.size(),
+                    hipMemcpyDeviceToHost));
+  const int cnt = static_cast<int>(std::min<unsigned long long>(t[0], (SCO_TRACE_SLOTS - 1) / 2));
+  *n = cnt;
+  for (int i = 0; i < cnt && i < max; ++i) {
+    if (ids) ids[i] = static_cast<int32_t>(t[2 * i + 1]);
+    if (us)  // marks: microseconds since the first mark; ids >= 900000 carry a raw value
+      us[i] = t[2 * i + 1] >= 900000 ? static_cast<double>(t[2 * i + 2])
+                                     : static_cast<double>(t[2 * i + 2] - t[2]) / c->wall_mhz;
   }
   return SCO_OK;
 }
@@ -529,9 +587,11 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   const int fr = consume_flags(c);
   const Layout& L = c->lay;
   unsigned long long* d_obs = at<unsigned long long>(c, L.off_obs);
+  uint32_t* d_used = at<uint32_t>(c, L.off_used);
   HIP_TRY(hipMemsetAsync(d_obs, 0, sizeof(unsigned long long) * 2 * c->n, c->stream));
+  HIP_TRY(hipMemsetAsync(d_used, 0, sizeof(uint32_t) * (SCO_MAXQ / 32) * c->n, c->stream));
   HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
-                             at<int8_t>(c, L.off_spin), d_obs, L.G));
+                             at<int8_t>(c, L.off_spin), at<uint16_t>(c, L.off_color), d_obs, d_used, L.G));
   for (int ci = 0; ci < c->n; ++ci) {
     const ChainDesc& d = c->cd[ci];
     const int t = L.chain_table[ci];
@@ -543,6 +603,8 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   std::vector<ChainState> st(c->n);
   std::vector<unsigned long long> sums(2 * c->n);
   std::vector<double> edip(c->n);
+  std::vector<uint32_t> used((SCO_MAXQ / 32) * c->n);
+  HIP_TRY(hipMemcpyAsync(used.data(), d_used, sizeof(uint32_t) * used.size(), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(sums.data(), d_obs, sizeof(unsigned long long) * 2 * c->n, hipMemcpyDeviceToHost, c->stream));
@@ -559,7 +621,9 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
     o.n_edges = s.n_edges / 2;
     o.delta_union = s.delta_union;
     o.q = s.q;
-    o.colors_used = s.colors_used;
+    int cu = 0;
+    for (int w = 0; w < SCO_MAXQ / 32; ++w) cu += __builtin_popcount(used[ci * (SCO_MAXQ / 32) + w]);
+    o.colors_used = c->graph_state == 2 ? cu : 0;
     o.kw_levels = s.M;
     int64_t r = 0;
     for (int p = 0; p < SCO_MAXLEVEL; ++p) r += s.kw_rounds[p];
@@ -594,6 +658,8 @@ int sco_get_graph(sco_ctx* c, int chain, int32_t* row_ptr, int32_t* col, int32_t
                   int64_t* n_dir) {
   if (!c || chain < 0 || chain >= c->n) return SCO_EINVAL;
   const int fr = consume_flags(c);
+  if (fr != SCO_OK) return fr;  // the graph of a flagged launch is not usable
+  if (c->graph_state < 1) return SCO_EINVAL;
   const ChainDesc& d = c->cd[chain];
   const Layout& L = c->lay;
   std::vector<int32_t> rp(d.N + 1);
@@ -601,6 +667,7 @@ int sco_get_graph(sco_ctx* c, int chain, int32_t* row_ptr, int32_t* col, int32_t
                          hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const int32_t e0 = rp[0], e1 = rp[d.N];
+  if (e0 < 0 || e1 < e0 || static_cast<int64_t>(e1) > 2 * static_cast<int64_t>(L.cap_und)) return SCO_EINTERNAL;
   if (n_dir) *n_dir = e1 - e0;
   if (row_ptr)
     for (int v = 0; v <= d.N; ++v) row_ptr[v] = rp[v] - e0;

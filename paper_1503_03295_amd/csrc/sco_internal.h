@@ -1,21 +1,26 @@
 // sco_internal.h -- layouts shared by the host runtime and the gfx950 kernels of libsco.
 //
 // Global site space: the chains' sites are concatenated, each chain starting at a
-// multiple of CHUNK so that a CHUNK-aligned run of global sites belongs to one chain
-// (chunk_chain[g / CHUNK]).  Padding sites (local index >= N) are never touched by
-// the method.
+// multiple of SCO_CHUNK so that a chunk of global sites belongs to one chain
+// (chunk_chain[g >> SCO_CHUNK_SHIFT]).  Padding sites (local index >= N) are never
+// touched by the method.  A chunk is exactly one block of the step kernel.
 #pragma once
 #include <stdint.h>
 
-#define SCO_CHUNK 256           // sites per chunk; a power of two
-#define SCO_CHUNK_SHIFT 8
+#include <hip/hip_runtime_api.h>
+
+#define SCO_CHUNK 1024          // sites per chunk == threads per block
+#define SCO_CHUNK_SHIFT 10
 #define SCO_MAXQ 256            // largest palette (Delta + 1) handled
-#define SCO_MAXLEVEL 64         // KW levels are at most ceil(log2(N)) <= 31
+#define SCO_MAXLEVEL 32         // KW levels are at most ceil(log2(N)) <= 31
+#define SCO_MAXCHAINS 256
+#define SCO_TILE_MAX 16384      // sites of a KW tile held in LDS (local levels)
 #define SCO_GUIDE_BITS 14       // guide table of the cumulative couplings: 2^14 buckets
+#define SCO_BAR_GROUPS 32       // first-level arrival groups of the grid barrier
 
 enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4 };
 
-enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4 };
+enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4, SCO_FLAG_STATE = 8 };
 
 // Immutable per-chain description (device copy written once by sco_init).
 struct ChainDesc {
@@ -29,7 +34,7 @@ struct ChainDesc {
   const double* delta;     // Vbar(+1) - Vbar(-1) per m (nullptr when hard)
   const float* delta32;    // delta rounded to FP32 (precision 1)
   double C_top, guide_inv; // C_{K-1}, NB / C_top
-  double twoJ, beta, inv_rate, neg_beta;
+  double twoJ, beta, inv_rate, neg_beta, inv_L;
   double pacc[9];          // exchange-only flips: index s_v * nn + 4; >= 1 means always accept
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
@@ -37,17 +42,22 @@ struct ChainDesc {
 
 // Mutable per-chain state written by the kernels.
 struct ChainState {
-  int32_t delta_union, q, M, colors_used;
-  uint32_t n_edges;        // undirected surviving bonds of the last switching
-  int32_t pad0;
+  int32_t delta_union, q, M, P;  // palette, KW levels, levels run inside one LDS tile
+  uint32_t n_edges;              // directed surviving bonds of the last switching
+  int32_t colors_used;
   unsigned long long accepted, attempts, rechecks, near_ties;
   int32_t kw_rounds[SCO_MAXLEVEL];
 };
 
-// Device-wide barrier words and flags.
+// Device-wide synchronisation words (each counter on its own 128-byte line).
 struct SyncWords {
-  uint32_t bar_count, bar_gen, flags, edge_count;
-  uint32_t qmax, mmax, pad[2];
+  uint32_t gen, pad0[31];
+  unsigned long long top, pad1[15];
+  unsigned long long grp[SCO_BAR_GROUPS * 16];
+  uint32_t flags, qmax, mmax;
+  uint32_t graph_valid;  // 1 once a switching phase completed (0 while one runs)
+  uint32_t color_valid;  // 1 once a colouring of the current graph completed
+  uint32_t pad2[27];
 };
 
 // Arguments of the persistent step kernel (all device pointers into the workspace).
@@ -57,30 +67,31 @@ struct StepArgs {
   SyncWords* sync;
   const int32_t* chunk_chain;
   int8_t* spin;
-  int32_t* deg;      // [G] degree, then the exclusive scan is written to row_ptr
-  int32_t* row_ptr;  // [G + 1]
-  int32_t* fill;     // [G] scatter cursors
+  int32_t* deg;           // [G] degrees (cleared by the switching phase)
+  int32_t* row_ptr;       // [G + 1]
+  int32_t* fill;          // [G] scatter cursors (cleared by the switching phase)
   int32_t *ea, *eb, *em;  // survivors: owner, partner (global sites), displacement index
-  int32_t* col;      // [2 * cap] neighbour (global site)
-  int32_t* attr;     // [2 * cap] displacement index
-  uint16_t* color;   // [G]
-  uint16_t* rho;     // [G] KW decision round of the current level
-  int32_t* g0;       // [G] level-0 group v / q
-  int32_t* plist;    // [G] per-block pending lists
-  int32_t* perm;     // [G] sites bucketed by colour (colour-major over all chains)
-  int32_t* hist;     // [SCO_MAXQ * nchunks + 1] colour histogram, scanned in place
-  int32_t* part;     // scan tile partials
+  int32_t* col;           // [2 * cap] neighbour (global site)
+  int32_t* attr;          // [2 * cap] displacement index
+  uint16_t* color;        // [G]
+  uint32_t* kw_word;      // [G] colouring state: level:5 | round:9 | colour:9
+  int32_t* plist;         // [G] per-block bucket lists
+  uint32_t* ecount;       // [nchunks] survivors found in each chunk (own region of cap/nchunks)
+  unsigned long long* scan_ts;  // decoupled look-back tile states
+  unsigned long long* trace;    // [SCO_TRACE_SLOTS] phase marks of block 0
   int64_t G;
   int32_t nchunks, n_chains;
-  uint32_t cap_und;  // undirected survivor capacity
-  int32_t nsw_override;  // >= 0: sweeps for every chain; < 0: each chain's n_sw
+  uint32_t cap_und;       // undirected survivor capacity (split evenly over the chunks)
+  int32_t nsw_override;   // >= 0: sweeps for every chain; < 0: each chain's n_sw
   int32_t nsw_max;
   uint32_t step;
+  uint32_t epoch;         // launch counter (tags the scan tile states)
 };
 
-enum : uint32_t { PH_SWITCH = 1u, PH_COLOR = 2u, PH_SWEEP = 4u };
+#define SCO_TRACE_SLOTS 512
+#define SCO_MAX_BLOCKS 4096
 
-#include <hip/hip_runtime_api.h>
+enum : uint32_t { PH_SWITCH = 1u, PH_COLOR = 2u, PH_SWEEP = 4u };
 
 // Host-side launchers of the kernels (defined next to the kernels).
 namespace sco_dev {
@@ -91,7 +102,8 @@ hipError_t init_spins(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_c
 int step_max_blocks();
 hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks);
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
-                     const int8_t* spin, unsigned long long* out, int64_t G);
+                     const int8_t* spin, const uint16_t* color, unsigned long long* out,
+                     unsigned* used, int64_t G);
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L,
                        int periodic, const int8_t* spin, int64_t vbase, uint32_t* bits,
                        double* prod, double* part, double* out);
