@@ -205,6 +205,8 @@ def main() -> int:
         "trace_us": trace,
         **extra,
     }
+    sco.close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
     return 0
 

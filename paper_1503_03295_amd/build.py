@@ -19,10 +19,19 @@ FLAGS = [
 ]
 
 
+DRIVER = os.path.join(HERE, "sco_drive")
+DRIVER_SRC = os.path.join(CSRC, "sco_drive.cpp")
+
+
 def build() -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, *FLAGS, "-o", tmp, *SOURCES])
     os.replace(tmp, LIB)
+    # native C-ABI driver (profiling, usage example), linked against the library
+    tmp = DRIVER + ".tmp"
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-Wall", "-o", tmp, DRIVER_SRC,
+                           f"-L{HERE}", "-lsco", f"-Wl,-rpath,{HERE}", "-Wl,-rpath,$ORIGIN"])
+    os.replace(tmp, DRIVER)
     return LIB
 
 

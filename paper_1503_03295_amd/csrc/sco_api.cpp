@@ -50,7 +50,7 @@ struct Layout {
   std::vector<size_t> off_theta, off_delta, off_delta32;
   size_t off_sync = 0, off_cd = 0, off_st = 0, off_chunk = 0, off_srcbase = 0;
   size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0;
-  size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_plist = 0, off_ecount = 0, off_trace = 0;
+  size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_ts = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
@@ -120,13 +120,13 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_attr = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
   lay.off_color = take(sizeof(uint16_t) * G);
   lay.off_word = take(sizeof(uint32_t) * G);
-  lay.off_plist = take(sizeof(int32_t) * G);
+  lay.off_rec = take(sizeof(int4) * G);
   lay.off_ecount = take(sizeof(uint32_t) * lay.nchunks);
   lay.off_trace = take(sizeof(unsigned long long) * SCO_TRACE_SLOTS);
   lay.ntiles = G / (16 * SCO_CHUNK) + 2;
   lay.off_ts = take(sizeof(unsigned long long) * lay.ntiles);
   lay.off_obs = take(sizeof(unsigned long long) * 2 * n);
-  lay.off_used = take(sizeof(uint32_t) * (SCO_MAXQ / 32) * n);
+  lay.off_used = take(sizeof(uint32_t) * SCO_QWORDS * n);
   int maxbits = 0;
   for (int c = 0; c < n; ++c) maxbits = std::max(maxbits, p[c].L * ((p[c].L + 31) / 32));
   lay.off_bits = take(sizeof(uint32_t) * maxbits);
@@ -466,7 +466,7 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   a.attr = at<int32_t>(c, L.off_attr);
   a.color = at<uint16_t>(c, L.off_color);
   a.kw_word = at<uint32_t>(c, L.off_word);
-  a.plist = at<int32_t>(c, L.off_plist);
+  a.rec = at<int4>(c, L.off_rec);
   a.ecount = at<uint32_t>(c, L.off_ecount);
   a.trace = nullptr;
   a.scan_ts = at<unsigned long long>(c, L.off_ts);
@@ -589,7 +589,7 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   unsigned long long* d_obs = at<unsigned long long>(c, L.off_obs);
   uint32_t* d_used = at<uint32_t>(c, L.off_used);
   HIP_TRY(hipMemsetAsync(d_obs, 0, sizeof(unsigned long long) * 2 * c->n, c->stream));
-  HIP_TRY(hipMemsetAsync(d_used, 0, sizeof(uint32_t) * (SCO_MAXQ / 32) * c->n, c->stream));
+  HIP_TRY(hipMemsetAsync(d_used, 0, sizeof(uint32_t) * SCO_QWORDS * c->n, c->stream));
   HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
                              at<int8_t>(c, L.off_spin), at<uint16_t>(c, L.off_color), d_obs, d_used, L.G));
   for (int ci = 0; ci < c->n; ++ci) {
@@ -603,7 +603,7 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   std::vector<ChainState> st(c->n);
   std::vector<unsigned long long> sums(2 * c->n);
   std::vector<double> edip(c->n);
-  std::vector<uint32_t> used((SCO_MAXQ / 32) * c->n);
+  std::vector<uint32_t> used(SCO_QWORDS * c->n);
   HIP_TRY(hipMemcpyAsync(used.data(), d_used, sizeof(uint32_t) * used.size(), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
                          c->stream));
@@ -622,7 +622,7 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
     o.delta_union = s.delta_union;
     o.q = s.q;
     int cu = 0;
-    for (int w = 0; w < SCO_MAXQ / 32; ++w) cu += __builtin_popcount(used[ci * (SCO_MAXQ / 32) + w]);
+    for (int w = 0; w < SCO_QWORDS; ++w) cu += __builtin_popcount(used[ci * SCO_QWORDS + w]);
     o.colors_used = c->graph_state == 2 ? cu : 0;
     o.kw_levels = s.M;
     int64_t r = 0;

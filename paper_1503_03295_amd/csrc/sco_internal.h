@@ -7,11 +7,12 @@
 #pragma once
 #include <stdint.h>
 
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #define SCO_CHUNK 1024          // sites per chunk == threads per block
 #define SCO_CHUNK_SHIFT 10
-#define SCO_MAXQ 256            // largest palette (Delta + 1) handled
+#define SCO_MAXQ 255            // largest palette (Delta + 1) handled: colours fit a byte
+#define SCO_QWORDS 8            // 32-bit words of a colour bitmask
 #define SCO_MAXLEVEL 32         // KW levels are at most ceil(log2(N)) <= 31
 #define SCO_MAXCHAINS 256
 #define SCO_TILE_MAX 16384      // sites of a KW tile held in LDS (local levels)
@@ -75,7 +76,7 @@ struct StepArgs {
   int32_t* attr;          // [2 * cap] displacement index
   uint16_t* color;        // [G]
   uint32_t* kw_word;      // [G] colouring state: level:5 | round:9 | colour:9
-  int32_t* plist;         // [G] per-block bucket lists
+  int4* rec;              // [G] per-block bucket lists: {site, row start, row end, chain}
   uint32_t* ecount;       // [nchunks] survivors found in each chunk (own region of cap/nchunks)
   unsigned long long* scan_ts;  // decoupled look-back tile states
   unsigned long long* trace;    // [SCO_TRACE_SLOTS] phase marks of block 0

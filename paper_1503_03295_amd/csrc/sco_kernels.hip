@@ -65,10 +65,20 @@ __device__ __forceinline__ int64_t gtid() {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// exact floor(v / d) for 0 <= v < 2^31, 1 <= d < 2^15, via a double reciprocal:
-// (v + 1/2) / d is at least 1/(2d) away from an integer, far above the rounding error.
+// exact floor(v / d) for 0 <= v < 2^31, 1 <= d < 2^20, via a double reciprocal:
+// (v + 1/2) / d is at least 1/(2d) away from an integer, while the two roundings
+// move the product by at most 2^31 2^-52 = 2^-21.
 __device__ __forceinline__ int fdiv(int v, double inv_d) {
   return static_cast<int>((static_cast<double>(v) + 0.5) * inv_d);
+}
+
+// exact floor(i / d) for 0 <= i < 2^16 and 2 <= d < 2^16 with m = ceil(2^32 / d):
+// i m / 2^32 exceeds i / d by less than i / 2^32 < 2^-16 < 1/d.
+__device__ __forceinline__ uint32_t magic16(uint32_t d) {
+  return static_cast<uint32_t>((0x100000000ull + d - 1u) / d);
+}
+__device__ __forceinline__ int div16(int i, uint32_t m) {
+  return static_cast<int>(__umulhi(static_cast<uint32_t>(i), m));
 }
 
 template <typename T>
@@ -103,7 +113,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // ~ seconds; reached only if residen
 // One wave per block fences: a release before arriving and an acquire after the
 // generation word moved, which makes every write of the block before the barrier
 // visible to every read after it.  Returns false once a wait has timed out.
-__device__ bool grid_barrier(SyncWords* s) {
+__device__ __forceinline__ bool grid_barrier(SyncWords* s) {
   __shared__ uint32_t s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -136,6 +146,48 @@ __device__ bool grid_barrier(SyncWords* s) {
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = timed_out(s) ? 0u : 1u;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Device-wide barrier between the colour classes of one phase, for data that is
+// written and read only with device-coherent (agent-scope) accesses: every wave waits
+// until its own stores have completed, then the same arrival and bounded wait as
+// grid_barrier, without the L2 write-back and invalidation of the agent-scope fences,
+// so data that no class writes stays cached.  Returns false once a wait has timed out.
+__device__ __forceinline__ bool class_barrier(SyncWords* s) {
+  __shared__ uint32_t s_ok;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nb = gridDim.x;
+    const uint32_t ng = nb < SCO_BAR_GROUPS ? nb : SCO_BAR_GROUPS;
+    const uint32_t grp = blockIdx.x % ng;
+    const uint32_t members = nb / ng + (grp < nb % ng ? 1u : 0u);
+    const uint32_t gen = ld_relaxed(&s->gen);
+    bool last = false;
+    const unsigned long long a =
+        __hip_atomic_fetch_add(&s->grp[grp * 16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+    if (a % members == 0) {
+      const unsigned long long t =
+          __hip_atomic_fetch_add(&s->top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+      last = (t % ng == 0);
+    }
+    if (last) {
+      st_relaxed(&s->gen, gen + 1u);
+    } else {
+      uint32_t n = 0;
+      while (ld_poll(&s->gen) == gen) {
+        if (timed_out(s)) break;
+        if (++n > kSpinLimit) {
+          set_flag(s, SCO_FLAG_TIMEOUT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
     s_ok = timed_out(s) ? 0u : 1u;
   }
   __syncthreads();
@@ -184,22 +236,21 @@ __device__ __forceinline__ int partner_of(int x, int y, int dx, int dy, int L, i
   return jy * L + jx;
 }
 
-// nearest neighbours (+x, -x, +y, -y); returns the count (open lattices: 2..4)
-__device__ __forceinline__ int nn_sites(int x, int y, int L, int periodic, int nb[4]) {
+// nearest neighbours in the slots (+x, -x, +y, -y); -1 where an open lattice ends
+// (fixed slots keep the array in registers)
+__device__ __forceinline__ void nn_sites(int x, int y, int L, int periodic, int nb[4]) {
   const int v = y * L + x;
   if (periodic) {
     nb[0] = y * L + (x + 1 == L ? 0 : x + 1);
     nb[1] = y * L + (x == 0 ? L - 1 : x - 1);
     nb[2] = (y + 1 == L ? 0 : y + 1) * L + x;
     nb[3] = (y == 0 ? L - 1 : y - 1) * L + x;
-    return 4;
+    return;
   }
-  int n = 0;
-  if (x + 1 < L) nb[n++] = v + 1;
-  if (x > 0) nb[n++] = v - 1;
-  if (y + 1 < L) nb[n++] = v + L;
-  if (y > 0) nb[n++] = v - L;
-  return n;
+  nb[0] = x + 1 < L ? v + 1 : -1;
+  nb[1] = x > 0 ? v - 1 : -1;
+  nb[2] = y + 1 < L ? v + L : -1;
+  nb[3] = y > 0 ? v - L : -1;
 }
 
 // max over the wave (all lanes must call)
@@ -305,6 +356,99 @@ extern "C" __global__ void __launch_bounds__(kBlock)
 }
 
 // =================================================================== step (1)
+// One owner's scan over the displacement table: the state of an in-flight site.
+struct Owner {
+  int64_t g;       // global site
+  int v, x, y, c;  // chain-local site, its coordinates, its chain
+  int pos;         // table index of the last candidate (-1 before the first draw)
+  uint32_t k;      // draws made
+  double Cpos;     // C at pos
+  uint32_t slo, shi;  // second half of the last Philox output: the next (odd) draw
+  int si;          // the owner's spin
+  bool live;
+};
+
+// Starts the next owner site of this thread in chunks [next, ch1); false when none
+// is left.
+__device__ __forceinline__ bool owner_take(const StepArgs& a, Owner& o, int& next, int ch1) {
+  while (next < ch1) {
+    const int64_t g = (static_cast<int64_t>(next) << SCO_CHUNK_SHIFT) + threadIdx.x;
+    const int c = a.chunk_chain[next];
+    ++next;
+    const ChainDesc& d = a.cd[c];
+    const int v = static_cast<int>(g - d.vbase);
+    if (v >= d.N) continue;  // chunk padding
+    o.g = g;
+    o.v = v;
+    o.c = c;
+    o.y = fdiv(v, d.inv_L);
+    o.x = v - o.y * d.L;
+    o.pos = -1;
+    o.k = 0;
+    o.Cpos = 0.0;
+    o.si = a.spin[g];
+    o.live = true;
+    return true;
+  }
+  o.live = false;
+  return false;
+}
+
+// One draw of a live owner: the next candidate (j, m) and whether it survives.  The
+// owner ends when the target passes C_top or the table is exhausted.
+__device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, int& m) {
+  const ChainDesc& d = a.cd[o.c];
+  const int K = d.K, NB = d.nguide;
+  if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
+    o.live = false;
+    return false;
+  }
+  uint32_t wlo, whi;
+  if ((o.k & 1u) == 0) {
+    const W4 r = philox10(a.step, static_cast<uint32_t>(o.v), o.k >> 1, SCO_TAG_SW, d.seed, d.chain_id);
+    wlo = r.x;
+    whi = r.y;
+    o.slo = r.z;
+    o.shi = r.w;
+  } else {
+    wlo = o.slo;
+    whi = o.shi;
+  }
+  const double u1 = unit52(wlo, whi);
+  const double target = o.Cpos + (-log(u1)) * d.inv_rate;
+  if (target > d.C_top) {
+    o.live = false;
+    return false;
+  }
+  const double* __restrict__ C = d.C;
+  int b = static_cast<int>(target * d.guide_inv);
+  b = b < 0 ? 0 : (b > NB ? NB : b);
+  int lo = d.guide[b > 0 ? b - 1 : 0];
+  int hi = (b + 2 <= NB) ? d.guide[b + 2] : K - 1;
+  lo = lo > o.pos + 1 ? lo : o.pos + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  m = lo;
+  const uint32_t p = d.hd[m];
+  const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
+  j = partner_of(o.x, o.y, dx, dy, d.L, d.periodic);
+  bool found = false;
+  if (j >= 0) {
+    found = o.si != a.spin[d.vbase + j];
+    if (!found && !d.hard) {
+      const W4 t = philox10(a.step, static_cast<uint32_t>(o.v), o.k, SCO_TAG_TH, d.seed, d.chain_id);
+      found = unit52(t.x, t.y) < d.theta[m];
+    }
+  }
+  o.pos = m;
+  o.Cpos = C[m];
+  ++o.k;
+  return found;
+}
+
 // One thread per owner site.  Candidate bonds of owner v: the table intervals
 // (C_{m-1}, C_m] hit by a Poisson process of rate (kappa+1) beta run from C = 0,
 // found by drawing exponential gaps E = -log(u) and locating C_pos + E T/(kappa+1)
@@ -312,97 +456,60 @@ extern "C" __global__ void __launch_bounds__(kBlock)
 // survives if its spins are antiparallel or, when kappa > 1, with probability
 // theta_m if they are parallel.  Draw k of owner v is half k&1 of
 // Philox(step, v, k>>1, SW); the thinning draw of candidate k is Philox(step, v, k, TH).
-__device__ void phase_switch(const StepArgs& a) {
+//
+// Block b owns a contiguous range of chunks; each thread keeps two owners of that
+// range in flight and starts the next one as soon as one ends, so a wave is not held
+// by its slowest owner.  Survivors go to the block's region (one LDS atomic per wave
+// and append); its count is written to the entry of the range's first chunk.
+__device__ __forceinline__ void phase_switch(const StepArgs& a) {
   __shared__ uint32_t s_count;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < a.G; base += stride) {
-    const int64_t g = base + threadIdx.x;  // a block-iteration is one chunk: one chain
-    const int64_t chunk = base >> SCO_CHUNK_SHIFT;
-    const uint32_t e_base = static_cast<uint32_t>(chunk) * cap_chunk;
-    if (threadIdx.x == 0) s_count = 0;
-    __syncthreads();
-    const ChainDesc& d = a.cd[a.chunk_chain[base >> SCO_CHUNK_SHIFT]];
-    const int v = static_cast<int>(g - d.vbase);
-    bool active = v < d.N;
-    const int L = d.L;
-    const int y = active ? fdiv(v, d.inv_L) : 0, x = v - y * L;
-    const int8_t si = active ? a.spin[g] : int8_t(0);
-    const double* __restrict__ C = d.C;
-    const double C_top = d.C_top, inv_rate = d.inv_rate, ginv = d.guide_inv;
-    const int K = d.K, NB = d.nguide;
-    int pos = -1;
-    double Cpos = 0.0;
-    uint32_t k = 0;
-    W4 r{0, 0, 0, 0};
-    while (true) {
-      bool found = false;
-      int j = -1, m = 0;
-      active = active && pos < K - 1;  // no candidate lies beyond the last table entry
-      if (active) {
-        if ((k & 1u) == 0)
-          r = philox10(a.step, static_cast<uint32_t>(v), k >> 1, SCO_TAG_SW, d.seed, d.chain_id);
-        const double u1 = (k & 1u) ? unit52(r.z, r.w) : unit52(r.x, r.y);
-        const double target = Cpos + (-log(u1)) * inv_rate;
-        if (target > C_top) {
-          active = false;
-        } else {
-          int b = static_cast<int>(target * ginv);
-          b = b < 0 ? 0 : (b > NB ? NB : b);
-          int lo = d.guide[b > 0 ? b - 1 : 0];
-          int hi = (b + 2 <= NB) ? d.guide[b + 2] : K - 1;
-          lo = lo > pos + 1 ? lo : pos + 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (C[mid] >= target) hi = mid;
-            else lo = mid + 1;
-          }
-          m = lo;
-          const uint32_t p = d.hd[m];
-          const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
-          j = partner_of(x, y, dx, dy, L, d.periodic);
-          if (j >= 0) {
-            found = si != a.spin[d.vbase + j];
-            if (!found && !d.hard) {
-              const W4 t = philox10(a.step, static_cast<uint32_t>(v), k, SCO_TAG_TH, d.seed, d.chain_id);
-              found = unit52(t.x, t.y) < d.theta[m];
-            }
-          }
-          pos = m;
-          Cpos = C[m];
-          ++k;
-        }
+  const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
+  const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
+  const uint32_t e_base = static_cast<uint32_t>(ch0) * cap_chunk;
+  const uint32_t cap_blk = static_cast<uint32_t>(ch1 - ch0) * cap_chunk;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  const uint32_t lane = lane_id();
+  auto append = [&](bool f, int64_t g, int c, int j, int m) {
+    const uint64_t mask = __ballot(f);
+    if (mask == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+    uint32_t e0 = 0;
+    if (static_cast<int>(lane) == leader) e0 = atomicAdd(&s_count, static_cast<uint32_t>(__popcll(mask)));
+    e0 = __shfl(e0, leader);
+    if (f) {
+      const uint32_t eo = e0 + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+      if (eo < cap_blk) {
+        const uint32_t e = e_base + eo;
+        const int32_t gj = static_cast<int32_t>(a.cd[c].vbase + j);
+        a.ea[e] = static_cast<int32_t>(g);
+        a.eb[e] = gj;
+        a.em[e] = m;
+        atomicAdd(&a.deg[g], 1);
+        atomicAdd(&a.deg[gj], 1);
+      } else {
+        set_flag(a.sync, SCO_FLAG_OVERFLOW);
       }
-      // wavefront-aggregated append into the block's region: one LDS atomic per wave
-      // and draw round
-      const uint64_t mask = __ballot(found);
-      if (mask) {
-        const uint32_t lane = lane_id();
-        const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-        uint32_t e0 = 0;
-        if (static_cast<int>(lane) == leader) e0 = atomicAdd(&s_count, static_cast<uint32_t>(__popcll(mask)));
-        e0 = __shfl(e0, leader);
-        if (found) {
-          const uint32_t eo = e0 + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
-          const uint32_t e = e_base + eo;
-          if (eo < cap_chunk) {
-            const int32_t gj = static_cast<int32_t>(d.vbase + j);
-            a.ea[e] = static_cast<int32_t>(g);
-            a.eb[e] = gj;
-            a.em[e] = m;
-            atomicAdd(&a.deg[g], 1);
-            atomicAdd(&a.deg[gj], 1);
-          } else {
-            set_flag(a.sync, SCO_FLAG_OVERFLOW);
-          }
-        }
-      }
-      if (__ballot(active) == 0) break;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) a.ecount[chunk] = min(s_count, cap_chunk);
-    __syncthreads();
+  };
+  int next = ch0;
+  Owner A, B;
+  owner_take(a, A, next, ch1);
+  owner_take(a, B, next, ch1);
+  while (__ballot(A.live || B.live) != 0) {
+    int jA = -1, mA = 0, jB = -1, mB = 0;
+    const bool fA = A.live && owner_draw(a, A, jA, mA);
+    const bool fB = B.live && owner_draw(a, B, jB, mB);
+    append(fA, A.g, A.c, jA, mA);
+    append(fB, B.g, B.c, jB, mB);
+    if (!A.live) owner_take(a, A, next, ch1);
+    if (!B.live) owner_take(a, B, next, ch1);
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? min(s_count, cap_blk) : 0u;
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ prefix sum
@@ -414,7 +521,7 @@ __device__ void phase_switch(const StepArgs& a) {
 constexpr int kItems = 16;
 constexpr int kTile = kBlock * kItems;
 
-__device__ bool scan_lookback(const int32_t* in, int64_t n, int32_t* out, unsigned long long* ts,
+__device__ __forceinline__ bool scan_lookback(const int32_t* in, int64_t n, int32_t* out, unsigned long long* ts,
                               uint32_t epoch, SyncWords* sync) {
   __shared__ int32_t wsum[kWaves];
   __shared__ int32_t s_excl;
@@ -493,10 +600,11 @@ __device__ bool scan_lookback(const int32_t* in, int64_t n, int32_t* out, unsign
 }
 
 // both directions of every survivor into the CSR
-__device__ void phase_scatter(const StepArgs& a) {
+__device__ __forceinline__ void phase_scatter(const StepArgs& a) {
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
+  const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
+  const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
+  for (int ch = ch0; ch < ch1; ++ch) {
     const uint32_t e0 = static_cast<uint32_t>(ch) * cap_chunk, e1 = e0 + a.ecount[ch];
     const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
     for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
@@ -513,12 +621,11 @@ __device__ void phase_scatter(const StepArgs& a) {
       a.attr[pw] = m;
     }
   }
-  (void)stride;
 }
 
 // Sorts each row ascending by neighbour; union degree |CSR(v) u NN(v)|; Delta and
 // directed bond count per chain.
-__device__ void phase_rowsort(const StepArgs& a) {
+__device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < a.G; base += stride) {
     const int c = a.chunk_chain[base >> SCO_CHUNK_SHIFT];
@@ -544,9 +651,11 @@ __device__ void phase_rowsort(const StepArgs& a) {
       }
       const int y = fdiv(v, d.inv_L), x = v - y * d.L;
       int nb[4];
-      const int n = nn_sites(x, y, d.L, d.periodic, nb);
+      nn_sites(x, y, d.L, d.periodic, nb);
       udeg = rowlen;
-      for (int q = 0; q < n; ++q) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (nb[q] < 0) continue;
         const int32_t gu = static_cast<int32_t>(d.vbase + nb[q]);
         bool dup = false;
         for (int b = r0; b < r1; ++b) dup |= (col[b] == gu);
@@ -576,28 +685,44 @@ __device__ void phase_rowsort(const StepArgs& a) {
 // Per chain: P = the levels whose groups (q 2^p sites, aligned) fit in one LDS tile
 // of T = q 2^P <= SCO_TILE_MAX sites; those run tile by tile entirely in LDS.  The
 // levels above P run over the whole site space with device-wide barriers between
-// colour classes.
+// colour classes, their pending sites spread evenly over the blocks.
 struct KwChain {
-  int q, M, P, tile0;  // tile0: first global tile of the chain
+  int q, M, P, tile0;  // palette, levels, levels inside a tile, first global tile
+  int L, N, periodic, pad;
+  int64_t vbase;
+  double inv_L, inv_q;
 };
 
-__device__ int kw_setup(const StepArgs& a, KwChain* kc, int* s_tiles) {
+struct KwShared {
+  KwChain kc[SCO_MAXCHAINS];
+  int ntiles, qmax, mmax, pmin;
+};
+
+__device__ __forceinline__ void kw_setup(const StepArgs& a, KwShared& ks) {
   // every block computes the same per-chain parameters (Delta is final here)
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
-    int q = a.st[c].delta_union + 1;
+    const ChainDesc& d = a.cd[c];
+    // every site has a nearest neighbour, so q >= 2 (the tile divisions rely on it)
+    int q = max(a.st[c].delta_union + 1, 2);
     if (q > SCO_MAXQ) {
       set_flag(a.sync, SCO_FLAG_PALETTE);
       q = SCO_MAXQ;
     }
-    const int N = a.cd[c].N;
-    const int groups = (N + q - 1) / q;
+    const int groups = (d.N + q - 1) / q;
     int M = 0;
     while ((1 << M) < groups) ++M;
     int P = 0;
     while (P < M && (q << (P + 1)) <= SCO_TILE_MAX) ++P;
-    kc[c].q = q;
-    kc[c].M = M;
-    kc[c].P = P;
+    KwChain& k = ks.kc[c];
+    k.q = q;
+    k.M = M;
+    k.P = P;
+    k.L = d.L;
+    k.N = d.N;
+    k.periodic = d.periodic;
+    k.vbase = d.vbase;
+    k.inv_L = d.inv_L;
+    k.inv_q = 1.0 / q;
     if (blockIdx.x == 0) {
       a.st[c].q = q;
       a.st[c].M = M;
@@ -606,208 +731,446 @@ __device__ int kw_setup(const StepArgs& a, KwChain* kc, int* s_tiles) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int t = 0;
-    uint32_t qmax = 0, mmax = 0;
+    int t = 0, qmax = 0, mmax = 0, pmin = SCO_MAXLEVEL;
     for (int c = 0; c < a.n_chains; ++c) {
-      kc[c].tile0 = t;
-      const int T = kc[c].q << kc[c].P;
-      t += (a.cd[c].N + T - 1) / T;
-      qmax = max(qmax, static_cast<uint32_t>(kc[c].q));
-      mmax = max(mmax, static_cast<uint32_t>(kc[c].M));
+      KwChain& k = ks.kc[c];
+      k.tile0 = t;
+      const int T = k.q << k.P;
+      t += (k.N + T - 1) / T;
+      qmax = max(qmax, k.q);
+      mmax = max(mmax, k.M);
+      pmin = min(pmin, k.P);
     }
-    *s_tiles = t;
+    ks.ntiles = t;
+    ks.qmax = qmax;
+    ks.mmax = mmax;
+    ks.pmin = pmin;
     if (blockIdx.x == 0) {
-      a.sync->qmax = qmax;
-      a.sync->mmax = mmax;
+      a.sync->qmax = static_cast<uint32_t>(qmax);
+      a.sync->mmax = static_cast<uint32_t>(mmax);
     }
   }
   __syncthreads();
-  return *s_tiles;
 }
 
+// pending sites of a chain of N sites at a level with half-group size h: the upper
+// halves [(2j+1) h, (2j+2) h) clipped to N
+__device__ __forceinline__ int64_t pending_count(int N, int64_t h) {
+  const int64_t full = N / (2 * h), rem = N - full * 2 * h;
+  return full * h + (rem > h ? rem - h : 0);
+}
+
+// Sites per thread whose loads are issued together: in colour classes (kBatch) and
+// in bucketing scans (kScan).
+constexpr int kBatch = 2;
+constexpr int kScan = 4;
+
+// In-tile bond partners held in LDS; a site whose list would end beyond this many
+// entries reads its row from global memory instead.
+constexpr int kAdjCap = 16384;
+
+// LDS of the colouring and sweep phases: the tile arrays of the local levels, or the
+// bucket list of a block (block-local offsets) in the global levels and the sweeps.
+struct TileLds {
+  uint8_t col[SCO_TILE_MAX];        // current colour
+  uint8_t rho[SCO_TILE_MAX];        // round of the decision (0: undecided)
+  uint16_t list[SCO_TILE_MAX / 2];  // pending sites bucketed by colour
+  uint16_t aoff[SCO_TILE_MAX + 1];  // in-tile bond list of site i: [aoff[i], aoff[i+1])
+  uint16_t adj[kAdjCap];
+};
+constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
+union PhaseLds {
+  TileLds tile;
+  int32_t list[kListCap];
+};
+
 // Levels 1..P of every tile, in LDS.  Groups up to level P are aligned to the tile,
-// so the same-group neighbours of a tile site are inside the tile.
-__device__ void phase_kw_local(const StepArgs& a, const KwChain* kc, int ntiles) {
-  __shared__ uint16_t t_col[SCO_TILE_MAX];
-  __shared__ uint16_t t_rho[SCO_TILE_MAX];
-  __shared__ uint16_t t_list[SCO_TILE_MAX];
+// so the same-group neighbours of a tile site are inside the tile; the tile's
+// in-tile bonds are staged once, so a level touches global memory only at its end.
+__device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared& ks, TileLds& tl) {
+  uint8_t* const t_col = tl.col;
+  uint8_t* const t_rho = tl.rho;
+  uint16_t* const t_list = tl.list;
+  uint16_t* const t_aoff = tl.aoff;
+  uint16_t* const t_adj = tl.adj;
   __shared__ int32_t t_off[SCO_MAXQ + 1];
   __shared__ int32_t t_fill[SCO_MAXQ];
+  __shared__ int32_t t_wsum[kWaves];
   __shared__ int32_t t_rounds;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const uint32_t lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  for (int tile = blockIdx.x; tile < ks.ntiles; tile += gridDim.x) {
     int c = 0;
-    while (c + 1 < a.n_chains && kc[c + 1].tile0 <= tile) ++c;
-    const int L = a.cd[c].L, periodic = a.cd[c].periodic, N = a.cd[c].N;
-    const int64_t vbase = a.cd[c].vbase;
-    const double inv_L = a.cd[c].inv_L;
-    const int q = kc[c].q, P = kc[c].P, T = q << P;
-    const double invq = 1.0 / q;
-    const int v0 = (tile - kc[c].tile0) * T;
-    const int n = min(T, N - v0);
-    for (int i = threadIdx.x; i < n; i += kBlock) t_col[i] = static_cast<uint16_t>(i - fdiv(i, invq) * q);
-    __syncthreads();
+    while (c + 1 < a.n_chains && ks.kc[c + 1].tile0 <= tile) ++c;
+    const KwChain& K = ks.kc[c];
+    const int q = K.q, P = K.P, T = q << P, L = K.L, periodic = K.periodic;
+    const int64_t vbase = K.vbase;
+    const int v0 = (tile - K.tile0) * T;
+    const int n = min(T, K.N - v0);
+    const int32_t gt0 = static_cast<int32_t>(vbase + v0);  // first global site of the tile
+    // tile indices and x0 + i are below 2^16, so the divisions by q, L and the
+    // half-group sizes are exact multiply-highs
+    const uint32_t mq = magic16(static_cast<uint32_t>(q)), mL = magic16(static_cast<uint32_t>(L));
+    const int y0 = fdiv(v0, K.inv_L), x0 = v0 - y0 * L;
+    for (int i = threadIdx.x; i < n; i += kBlock) t_col[i] = static_cast<uint8_t>(i - div16(i, mq) * q);
+    if (P > 0) {
+      // in-tile partner counts, then offsets (block scan), then the partners in row order
+      for (int i = threadIdx.x; i < n; i += kBlock) {
+        const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        int k = 0;
+        for (int e = r0; e < r1; ++e) {
+          const int j = a.col[e] - gt0;
+          k += (j >= 0 && j < n) ? 1 : 0;
+        }
+        t_aoff[i + 1] = static_cast<uint16_t>(k);
+      }
+      __syncthreads();
+      {
+        constexpr int kPer = SCO_TILE_MAX / kBlock;
+        const int b0 = 1 + static_cast<int>(threadIdx.x) * kPer;
+        int s = 0;
+        for (int k = 0; k < kPer; ++k)
+          if (b0 + k <= n) s += t_aoff[b0 + k];
+        int incl = s;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int x = __shfl_up(incl, o);
+          if (lane >= static_cast<uint32_t>(o)) incl += x;
+        }
+        if (lane == 63) t_wsum[wave] = incl;
+        __syncthreads();
+        int run = incl - s;
+        for (int w = 0; w < wave; ++w) run += t_wsum[w];
+        for (int k = 0; k < kPer; ++k)
+          if (b0 + k <= n) {
+            run += t_aoff[b0 + k];
+            t_aoff[b0 + k] = static_cast<uint16_t>(min(run, 65535));
+          }
+        if (threadIdx.x == 0) t_aoff[0] = 0;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += kBlock) {
+        const int e_end = t_aoff[i + 1];
+        if (e_end > kAdjCap) continue;  // read from global memory when needed
+        int w = t_aoff[i];
+        const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        for (int e = r0; e < r1 && w < e_end; ++e) {
+          const int j = a.col[e] - gt0;
+          if (j >= 0 && j < n) t_adj[w++] = static_cast<uint16_t>(j);
+        }
+      }
+      __syncthreads();
+    }
+    if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 30);
     for (int p = 1; p <= P; ++p) {
+      // pending sites: k -> (2 (k / H) + 1) H + k mod H, H = q 2^(p-1) the half-group
+      const int H = q << (p - 1);
+      const uint32_t mH = magic16(static_cast<uint32_t>(H));
+      const int npend = static_cast<int>(pending_count(n, H));
       for (int k = threadIdx.x; k <= q; k += kBlock) t_off[k] = 0;
       if (threadIdx.x == 0) t_rounds = 0;
       __syncthreads();
-      for (int i = threadIdx.x; i < n; i += kBlock)
-        if ((fdiv(i, invq) >> (p - 1)) & 1) atomicAdd(&t_off[t_col[i] + 1], 1);
+      for (int k = threadIdx.x; k < npend; k += kBlock) {
+        const int j = div16(k, mH);
+        atomicAdd(&t_off[t_col[(2 * j + 1) * H + (k - j * H)] + 1], 1);
+      }
       __syncthreads();
-      if (threadIdx.x == 0)
-        for (int k = 0; k < q; ++k) t_off[k + 1] += t_off[k];
-      __syncthreads();
+      if (wave == 0) {  // exclusive prefix of the q <= 255 counts, four per lane
+        int cnt[4], s = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int idx = 1 + 4 * static_cast<int>(lane) + r;
+          cnt[r] = idx <= q ? t_off[idx] : 0;
+          s += cnt[r];
+        }
+        int incl = s;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int x = __shfl_up(incl, o);
+          if (lane >= static_cast<uint32_t>(o)) incl += x;
+        }
+        int run = incl - s;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int idx = 1 + 4 * static_cast<int>(lane) + r;
+          run += cnt[r];
+          if (idx <= q) t_off[idx] = run;
+        }
+      }
       for (int k = threadIdx.x; k < q; k += kBlock) t_fill[k] = 0;
       __syncthreads();
-      for (int i = threadIdx.x; i < n; i += kBlock)
-        if ((fdiv(i, invq) >> (p - 1)) & 1) {
-          const int cc = t_col[i];
-          t_list[t_off[cc] + atomicAdd(&t_fill[cc], 1)] = static_cast<uint16_t>(i);
-          t_rho[i] = 0;
-        }
+      if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 60 + p);
+      for (int k = threadIdx.x; k < npend; k += kBlock) {
+        const int j = div16(k, mH);
+        const int i = (2 * j + 1) * H + (k - j * H);
+        const int cc = t_col[i];
+        t_list[t_off[cc] + atomicAdd(&t_fill[cc], 1)] = static_cast<uint16_t>(i);
+        t_rho[i] = 0;
+      }
       __syncthreads();
+      if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 80 + p);
       for (int cc = q - 1; cc >= 0; --cc) {
         int tmax = 0;
         for (int k = t_off[cc] + threadIdx.x; k < t_off[cc + 1]; k += kBlock) {
           const int i = t_list[k];
-          const int v = v0 + i;
-          const int grp = fdiv(i, invq) >> p;
-          const int y = fdiv(v, inv_L), x = v - y * L;
-          int nb[4];
-          const int nn = nn_sites(x, y, L, periodic, nb);
-          const int64_t g = vbase + v;
-          const int r0 = a.row_ptr[g], r1 = a.row_ptr[g + 1];
+          const int grp = div16(i, mq) >> p;
           ColorSet taken;
           int rmax = 0;
-          for (int t = 0; t < nn + (r1 - r0); ++t) {
-            const int u = t < nn ? nb[t] : static_cast<int>(a.col[r0 + t - nn] - vbase);
-            const int j = u - v0;
-            if (j < 0 || j >= n) continue;  // outside the tile: another group
-            const int gj = fdiv(j, invq);
-            if ((gj >> p) != grp) continue;
+          // neighbour j (tile index): same group only; a pending one counts once decided
+          auto visit = [&](int j) {
+            if (j < 0 || j >= n) return;  // outside the tile: another group
+            const int gj = div16(j, mq);
+            if ((gj >> p) != grp) return;
             if ((gj >> (p - 1)) & 1) {
               const int rj = t_rho[j];
-              if (rj == 0) continue;  // pending, undecided: a smaller colour
+              if (rj == 0) return;  // pending, undecided: a smaller colour
               rmax = max(rmax, rj);
             }
             taken.add(t_col[j]);
+          };
+          const int t = x0 + i, dy = div16(t, mL);
+          int nb[4];
+          nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (nb[u] >= 0) visit(nb[u] - v0);
+          const int e0 = t_aoff[i], e1 = t_aoff[i + 1];
+          if (e1 <= kAdjCap) {
+            for (int e = e0; e < e1; ++e) visit(t_adj[e]);
+          } else {
+            const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+            for (int e = r0; e < r1; ++e) visit(a.col[e] - gt0);
           }
           int nc = taken.first_free();
           if (nc >= q) {
             set_flag(a.sync, SCO_FLAG_PALETTE);
             nc = q - 1;
           }
-          t_col[i] = static_cast<uint16_t>(nc);
-          t_rho[i] = static_cast<uint16_t>(rmax + 1);
+          t_col[i] = static_cast<uint8_t>(nc);
+          t_rho[i] = static_cast<uint8_t>(rmax + 1);
           tmax = max(tmax, rmax + 1);
         }
         tmax = wave_max(tmax);
-        if (lane_id() == 0 && tmax > 0) atomicMax(&t_rounds, tmax);
+        if (lane == 0 && tmax > 0) atomicMax(&t_rounds, tmax);
         __syncthreads();
       }
       if (threadIdx.x == 0 && t_rounds > 0) atomicMax(&a.st[c].kw_rounds[p], t_rounds);
+      if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 40 + p);
     }
     const uint32_t tag = static_cast<uint32_t>(P) << 18;
     for (int i = threadIdx.x; i < n; i += kBlock) {
-      const int64_t g = vbase + v0 + i;
-      a.color[g] = t_col[i];
-      a.kw_word[g] = tag | t_col[i];
+      a.color[gt0 + i] = t_col[i];
+      a.kw_word[gt0 + i] = tag | t_col[i];
     }
     __syncthreads();
   }
 }
 
-// Levels P+1..M over the whole site space.  Block b owns the sites [b S, (b+1) S)
-// and buckets its pending sites of the level by colour into plist; device-wide
-// barriers separate the colour classes, so every read sees the writes of the classes
-// before it.  kw_word[g] holds (level << 18) | (round << 9) | colour of the last
-// level that decided g, so "decided at this level" needs no clearing pass.  A colour
-// read from memory is checked against the palette before it is used as an index.
-__device__ bool phase_kw_global(const StepArgs& a, const KwChain* kc) {
+// Levels P+1..M over the whole site space.  The pending sites of a level, numbered
+// chain by chain, are split evenly over the blocks; a block buckets its share by
+// colour into a list of block-local offsets (in LDS when it fits), then the colour
+// classes run largest first with a device-wide barrier after each, so every read sees
+// the decisions of the classes before it.  kw_word[g] holds (level << 18) |
+// (round << 9) | colour of the last level that decided g, so "decided at this level"
+// needs no clearing pass.  A colour read from memory is checked against the palette
+// before it is used as an index.
+__device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShared& ks, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
   __shared__ int32_t bfill[SCO_MAXQ];
   __shared__ int32_t brounds[SCO_MAXCHAINS];
-  const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
-  const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
-  const int64_t r1 = min(r0 + S, a.G);
-  const int qmax = static_cast<int>(a.sync->qmax);
-  const int mmax = static_cast<int>(a.sync->mmax);
-  int pmin = SCO_MAXLEVEL;
-  for (int c = 0; c < a.n_chains; ++c) pmin = min(pmin, kc[c].P);
+  __shared__ long long cpre[SCO_MAXCHAINS + 1];
+  __shared__ long long wtot[kWaves];
+  const uint32_t lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int nch = a.n_chains, qmax = ks.qmax;
 
-  for (int p = pmin + 1; p <= mmax; ++p) {
-    for (int k = threadIdx.x; k <= qmax; k += kBlock) boff[k] = 0;
-    for (int c = threadIdx.x; c < a.n_chains; c += kBlock) brounds[c] = 0;
-    __syncthreads();
+  for (int p = ks.pmin + 1; p <= ks.mmax; ++p) {
+    // pending counts per chain, exclusive prefix over the chains
+    {
+      long long np = 0;
+      const int c = tid;
+      if (c < nch) {
+        const KwChain& K = ks.kc[c];
+        if (p > K.P && p <= K.M) np = pending_count(K.N, static_cast<int64_t>(K.q) << (p - 1));
+      }
+      long long incl = np;
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long x = __shfl_up(incl, o);
+        if (lane >= static_cast<uint32_t>(o)) incl += x;
+      }
+      if (lane == 63) wtot[wave] = incl;
+      __syncthreads();
+      long long off = 0;
+      for (int w = 0; w < wave; ++w) off += wtot[w];
+      if (c < nch) cpre[c] = off + incl - np;
+      if (c == nch - 1) cpre[nch] = off + incl;
+      for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
+      for (int k = tid; k < nch; k += kBlock) brounds[k] = 0;
+      __syncthreads();
+    }
+    const long long tot = cpre[nch];
+    const long long k0 = tot * blockIdx.x / gridDim.x, k1 = tot * (blockIdx.x + 1) / gridDim.x;
+    // the block's list: LDS when its share fits, else its own range of the records
+    int32_t* lst = (k1 - k0 <= kListCap) ? lds_list : reinterpret_cast<int32_t*>(a.rec) + k0;
+    // pending index -> chain and chain-local site
+    auto site_of = [&](long long k, int& c, int& v) {
+      int lo = 0, hi = nch - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cpre[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      c = lo;
+      const uint32_t kk = static_cast<uint32_t>(k - cpre[c]);
+      const uint32_t h = static_cast<uint32_t>(ks.kc[c].q) << (p - 1);
+      const uint32_t j = kk / h;
+      v = static_cast<int>((2u * j + 1u) * h + (kk - j * h));
+    };
     for (int pass = 0; pass < 2; ++pass) {
-      for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) {
-        const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-        const int v = static_cast<int>(g - a.cd[c].vbase);
-        if (v >= a.cd[c].N || p <= kc[c].P || p > kc[c].M) continue;
-        const int gg = fdiv(v, 1.0 / kc[c].q);
-        if (((gg >> (p - 1)) & 1) == 0) continue;
-        const int cc = a.color[g];
-        if (cc >= kc[c].q) {  // cannot happen after a complete colouring
-          set_flag(a.sync, SCO_FLAG_PALETTE);
-          continue;
+      // kScan sites per thread and iteration, their loads issued together
+      for (long long kb = k0; kb < k1; kb += kScan * kBlock) {
+        int cs[kScan], col[kScan];
+        bool ok[kScan];
+#pragma unroll
+        for (int r = 0; r < kScan; ++r) {
+          const long long k = kb + r * kBlock + tid;
+          ok[r] = k < k1;
+          cs[r] = 0;
+          col[r] = 0;
+          if (ok[r]) {
+            int v;
+            site_of(k, cs[r], v);
+            col[r] = a.color[ks.kc[cs[r]].vbase + v];
+          }
         }
-        if (pass == 0) atomicAdd(&boff[cc + 1], 1);
-        else a.plist[r0 + boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(g);
+#pragma unroll
+        for (int r = 0; r < kScan; ++r) {
+          if (!ok[r]) continue;
+          const int cc = col[r];
+          if (cc >= ks.kc[cs[r]].q) {  // cannot happen after a complete colouring
+            set_flag(a.sync, SCO_FLAG_PALETTE);
+            continue;
+          }
+          if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+          else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(kb + r * kBlock + tid - k0);
+        }
       }
       __syncthreads();
       if (pass == 0) {
         if (threadIdx.x == 0)
           for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-        for (int k = threadIdx.x; k < qmax; k += kBlock) bfill[k] = 0;
+        for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
         __syncthreads();
       }
     }
+    mark(a.trace, 200 + p);
     for (int cc = qmax - 1; cc >= 0; --cc) {
-      // every thread of the block runs the same number of iterations
-      for (int kb = boff[cc]; kb < boff[cc + 1]; kb += kBlock) {
-        const int k = kb + static_cast<int>(threadIdx.x);
-        int cdone = -1, rdone = 0;
-        if (k < boff[cc + 1]) {
-        const int32_t g = a.plist[r0 + k];
-        const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-        const int L = a.cd[c].L, periodic = a.cd[c].periodic;
-        const int64_t vbase = a.cd[c].vbase;
-        const int q = kc[c].q;
-        const double invq = 1.0 / q;
-        const int v = static_cast<int>(g - vbase);
-        const int grp = fdiv(v, invq) >> p;
-        const int y = fdiv(v, a.cd[c].inv_L), x = v - y * L;
-        int nb[4];
-        const int nn = nn_sites(x, y, L, periodic, nb);
-        ColorSet taken;
-        int rmax = 0;
-        const int r0e = a.row_ptr[g], r1e = a.row_ptr[g + 1];
-        for (int t = 0; t < nn + (r1e - r0e); ++t) {
-          const int u = t < nn ? nb[t] : static_cast<int>(a.col[r0e + t - nn] - vbase);
-          const int gu = fdiv(u, invq);
-          if ((gu >> p) != grp) continue;  // another group at this level
-          if ((gu >> (p - 1)) & 1) {       // pending at this level
-            const uint32_t w = a.kw_word[vbase + u];
-            if (static_cast<int>((w >> 18) & 0x1Fu) != p) continue;  // undecided: a smaller colour
-            rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
+      const int b0 = boff[cc], b1 = boff[cc + 1];
+      // every thread of the block runs the same number of iterations; each takes
+      // kBatch sites of the class and loads everything they read before deciding any
+      // (sites of one class never read each other's words)
+      for (int kb = b0; kb < b1; kb += kBatch * kBlock) {
+        int gs[kBatch], cs[kBatch], rb[kBatch], re[kBatch];
+        int nbs[kBatch][4];
+        uint32_t wn[kBatch][4];
+        bool ok[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int kx = kb + r * kBlock + tid;
+          ok[r] = kx < b1;
+          gs[r] = 0;
+          cs[r] = 0;
+          rb[r] = re[r] = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            nbs[r][t] = -1;
+            wn[r][t] = 0;
           }
-          taken.add(a.color[vbase + u]);
+          if (ok[r]) {
+            int v;
+            site_of(k0 + lst[kx], cs[r], v);
+            const KwChain& K = ks.kc[cs[r]];
+            const int32_t vb = static_cast<int32_t>(K.vbase);
+            gs[r] = vb + v;
+            const int y = fdiv(v, K.inv_L), x = v - y * K.L;
+            nn_sites(x, y, K.L, K.periodic, nbs[r]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
+            rb[r] = a.row_ptr[gs[r]];
+            re[r] = a.row_ptr[gs[r] + 1];
+          }
         }
-        int nc = taken.first_free();
-        if (nc >= q) {
-          set_flag(a.sync, SCO_FLAG_PALETTE);
-          nc = q - 1;
+        // the first two bond partners and their words
+        int pb[kBatch][2];
+        uint32_t wb[kBatch][2];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+          pb[r][0] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
+          pb[r][1] = re[r] > rb[r] + 1 ? a.col[rb[r] + 1] - vb : -1;
         }
-        a.color[g] = static_cast<uint16_t>(nc);
-        a.kw_word[g] = (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
-                       static_cast<uint32_t>(nc);
-        cdone = c;
-        rdone = rmax + 1;
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) wb[r][t] = pb[r][t] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r][t]]) : 0u;
         }
-        wave_max_to(brounds, cdone, rdone);
+        int cdone[kBatch], rdone[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          cdone[r] = -1;
+          rdone[r] = 0;
+          if (!ok[r]) continue;
+          const int32_t g = gs[r];
+          const int c = cs[r];
+          const KwChain& K = ks.kc[c];
+          const int q = K.q;
+          const int32_t vb = static_cast<int32_t>(K.vbase);
+          const int grp = fdiv(g - vb, K.inv_q) >> p;
+          ColorSet taken;
+          int rmax = 0;
+          // neighbour u (chain-local) with word w: same group only; a pending one
+          // counts once decided at this level
+          auto visit = [&](int u, uint32_t w) {
+            const int gu = fdiv(u, K.inv_q);
+            if ((gu >> p) != grp) return;  // another group at this level
+            if ((gu >> (p - 1)) & 1) {     // pending at this level
+              if (static_cast<int>((w >> 18) & 0x1Fu) != p) return;  // undecided: a smaller colour
+              rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
+            }
+            taken.add(static_cast<int>(w & 0x1FFu));
+          };
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (nbs[r][t] >= 0) visit(nbs[r][t], wn[r][t]);
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+            if (pb[r][t] >= 0) visit(pb[r][t], wb[r][t]);
+          for (int e = rb[r] + 2; e < re[r]; ++e) {
+            const int u = a.col[e] - vb;
+            visit(u, ld_relaxed(&a.kw_word[vb + u]));
+          }
+          int nc = taken.first_free();
+          if (nc >= q) {
+            set_flag(a.sync, SCO_FLAG_PALETTE);
+            nc = q - 1;
+          }
+          a.color[g] = static_cast<uint16_t>(nc);
+          st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
+                                        static_cast<uint32_t>(nc));
+          cdone[r] = c;
+          rdone[r] = rmax + 1;
+        }
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
       }
-      if (!grid_barrier(a.sync)) return false;
+      if (p == ks.pmin + 1) mark(a.trace, 300 + 2 * cc);
+      // between the classes of a level only the words change (coherent accesses); the
+      // level ends with a full barrier that also publishes the colours
+      if (!(cc > 0 ? class_barrier(a.sync) : grid_barrier(a.sync))) return false;
+      if (p == ks.pmin + 1) mark(a.trace, 301 + 2 * cc);
     }
-    for (int c = threadIdx.x; c < a.n_chains; c += kBlock)
+    for (int c = tid; c < nch; c += kBlock)
       if (brounds[c] > 0) atomicMax(&a.st[c].kw_rounds[p], brounds[c]);
     mark(a.trace, 100 + p);
   }
@@ -815,116 +1178,176 @@ __device__ bool phase_kw_global(const StepArgs& a, const KwChain* kc) {
 }
 
 // =================================================================== step (3)
-// Block b buckets its own sites [b S, (b+1) S) by colour, then the colour classes are
-// swept in ascending order with device-wide barriers between them.  Flipping s_v
-// changes H' by s_v h_v, h_v = 2J sum_NN s_u - sum_bonds delta_m s_u (NN first, then
-// the bonds in row order); with kappa == 1 a bond is hard and forbids the flip, and
-// the exchange-only acceptance is the table pacc.
-__device__ bool phase_sweep(const StepArgs& a) {
+// Block b buckets its own sites [b S, (b+1) S) by colour into a list of block-local
+// offsets (in LDS when it fits), then the colour classes are swept in ascending order
+// with device-wide barriers between them.  Flipping s_v changes H' by s_v h_v,
+// h_v = 2J sum_NN s_u - sum_bonds delta_m s_u (NN first, then the bonds in row
+// order); with kappa == 1 a bond is hard and forbids the flip, and the exchange-only
+// acceptance is the table pacc.
+constexpr int kLocalChains = 4;  // chain descriptors of a block's range held in LDS
+
+__device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
   __shared__ int32_t bfill[SCO_MAXQ];
   __shared__ unsigned long long bacc[SCO_MAXCHAINS];  // accepted flips of the block per chain
+  __shared__ ChainDesc lcd[kLocalChains];
   const int qmax = static_cast<int>(a.sync->qmax);
   const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
   const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
   const int64_t r1 = min(r0 + S, a.G);
-  for (int k = threadIdx.x; k <= qmax; k += kBlock) boff[k] = 0;
-  for (int c = threadIdx.x; c < a.n_chains; c += kBlock) bacc[c] = 0;
+  const int tid = static_cast<int>(threadIdx.x);
+  int32_t* lst = (r1 - r0 <= kListCap) ? lds_list : reinterpret_cast<int32_t*>(a.rec) + r0;
+  // the chains of the block's range are a contiguous run [c_lo, c_hi]
+  const int c_lo = r0 < r1 ? a.chunk_chain[r0 >> SCO_CHUNK_SHIFT] : 0;
+  const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
+  const bool local_cd = c_hi - c_lo < kLocalChains;
+  if (local_cd)
+    for (int i = tid; i <= c_hi - c_lo; i += kBlock) lcd[i] = a.cd[c_lo + i];
+  for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
+  for (int c = tid; c < a.n_chains; c += kBlock) bacc[c] = 0;
   __syncthreads();
-  for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) {
-    const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-    if (static_cast<int>(g - a.cd[c].vbase) < a.cd[c].N) {
-      const int cc = a.color[g];
-      if (cc < qmax) atomicAdd(&boff[cc + 1], 1);
-      else set_flag(a.sync, SCO_FLAG_PALETTE);  // cannot happen after a complete colouring
+  auto desc = [&](int c) -> const ChainDesc& { return local_cd ? lcd[c - c_lo] : a.cd[c]; };
+  // colour buckets of the block's sites: count, offsets, list (kScan sites per thread
+  // and iteration, their loads issued together)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t gb = r0; gb < r1; gb += kScan * kBlock) {
+      int col[kScan];
+      bool ok[kScan];
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        const int64_t g = gb + r * kBlock + tid;
+        ok[r] = false;
+        col[r] = 0;
+        if (g < r1) {
+          const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+          const ChainDesc& d = desc(c);
+          ok[r] = static_cast<int>(g - d.vbase) < d.N;
+          if (ok[r]) col[r] = a.color[g];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        if (!ok[r]) continue;
+        const int cc = col[r];
+        if (cc >= qmax) {  // cannot happen after a complete colouring
+          if (pass == 0) set_flag(a.sync, SCO_FLAG_PALETTE);
+          continue;
+        }
+        if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+        else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(gb + r * kBlock + tid - r0);
+      }
+    }
+    __syncthreads();
+    if (pass == 0) {
+      if (threadIdx.x == 0)
+        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
+      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
+      __syncthreads();
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-  for (int k = threadIdx.x; k < qmax; k += kBlock) bfill[k] = 0;
-  __syncthreads();
-  for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) {
-    const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-    if (static_cast<int>(g - a.cd[c].vbase) < a.cd[c].N) {
-      const int cc = a.color[g];
-      if (cc < qmax) a.plist[r0 + boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(g);
-    }
-  }
-  __syncthreads();
   mark(a.trace, 22);
 
   for (int s = 0; s < a.nsw_max; ++s) {
     for (int cc = 0; cc < qmax; ++cc) {
       const int k0 = boff[cc], k1 = boff[cc + 1];
-      // every thread of the block runs the same number of iterations
-      for (int kb = k0; kb < k1; kb += kBlock) {
-        const int k = kb + static_cast<int>(threadIdx.x);
-        bool acc = false;
-        int c = -1;
-        if (k < k1) {
-          const int32_t g = a.plist[r0 + k];
-          c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-          const ChainDesc& d = a.cd[c];
-          const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
-          if (s < nsw) {
-            const int v = static_cast<int>(g - d.vbase);
-            const int y = fdiv(v, d.inv_L), x = v - y * d.L;
-            int nb[4];
-            const int n = nn_sites(x, y, d.L, d.periodic, nb);
-            int nn = 0;
-            for (int t = 0; t < n; ++t) nn += a.spin[d.vbase + nb[t]];
-            const int8_t sv = a.spin[g];
-            const int q0 = a.row_ptr[g], q1 = a.row_ptr[g + 1];
-            if (d.hard) {
-              if (q1 == q0) {
-                const double pa = d.pacc[sv * nn + 4];
-                if (pa >= 1.0) {
-                  acc = true;
-                } else {
-                  const W4 r = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s),
-                                        SCO_TAG_MC, d.seed, d.chain_id);
-                  acc = unit52(r.x, r.y) < pa;
-                }
-              }
-            } else {
-              double h = d.twoJ * static_cast<double>(nn);
-              for (int t = q0; t < q1; ++t) {
-                const double dm = d.delta[a.attr[t]];
-                h = a.spin[a.col[t]] > 0 ? h - dm : h + dm;
-              }
-              const double dE = sv > 0 ? h : -h;
-              if (dE <= 0.0) {
-                acc = true;
-              } else {
-                const W4 r = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s),
-                                      SCO_TAG_MC, d.seed, d.chain_id);
-                const double u = unit52(r.x, r.y);
-                const double pr = exp(d.neg_beta * dE);
-                if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
-                acc = u < pr;
-              }
+      // every thread of the block runs the same number of iterations; each takes
+      // kBatch sites of the class and loads their neighbour spins before deciding
+      // (sites of one class are not coupled)
+      for (int kb = k0; kb < k1; kb += kBatch * kBlock) {
+        int64_t gs[kBatch];
+        int cs[kBatch], nsum[kBatch], sv[kBatch], q0[kBatch], q1[kBatch];
+        bool live[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int k = kb + r * kBlock + tid;
+          live[r] = false;
+          gs[r] = 0;
+          cs[r] = 0;
+          nsum[r] = sv[r] = q0[r] = q1[r] = 0;
+          if (k < k1) {
+            gs[r] = r0 + lst[k];
+            cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
+            const ChainDesc& d = desc(cs[r]);
+            const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
+            live[r] = s < nsw;
+            if (live[r]) {
+              const int v = static_cast<int>(gs[r] - d.vbase);
+              const int y = fdiv(v, d.inv_L), x = v - y * d.L;
+              int nb[4];
+              nn_sites(x, y, d.L, d.periodic, nb);
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (nb[t] >= 0) nsum[r] += ld_relaxed(&a.spin[d.vbase + nb[t]]);
+              sv[r] = ld_relaxed(&a.spin[gs[r]]);
+              q0[r] = a.row_ptr[gs[r]];
+              q1[r] = a.row_ptr[gs[r] + 1];
             }
-            if (acc) a.spin[g] = static_cast<int8_t>(-sv);
           }
         }
+        bool acc[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          acc[r] = false;
+          if (!live[r]) continue;
+          const int64_t g = gs[r];
+          const int c = cs[r];
+          const ChainDesc& d = desc(c);
+          const int v = static_cast<int>(g - d.vbase);
+          if (d.hard) {
+            if (q1[r] == q0[r]) {
+              const double pa = d.pacc[sv[r] * nsum[r] + 4];
+              if (pa >= 1.0) {
+                acc[r] = true;
+              } else {
+                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                      d.seed, d.chain_id);
+                acc[r] = unit52(w.x, w.y) < pa;
+              }
+            }
+          } else {
+            double h = d.twoJ * static_cast<double>(nsum[r]);
+            for (int t = q0[r]; t < q1[r]; ++t) {
+              const double dm = d.delta[a.attr[t]];
+              h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+            }
+            const double dE = sv[r] > 0 ? h : -h;
+            if (dE <= 0.0) {
+              acc[r] = true;
+            } else {
+              const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                    d.seed, d.chain_id);
+              const double u = unit52(w.x, w.y);
+              const double pr = exp(d.neg_beta * dE);
+              if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
+              acc[r] = u < pr;
+            }
+          }
+          if (acc[r]) st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
+        }
         // accepted flips per chain into LDS: one atomic per wave when the wave is one chain
-        const int c0 = __shfl(c, 0);
-        if (__ballot(c != c0 && c >= 0) == 0) {
-          const uint64_t mk = __ballot(acc);
-          if (lane_id() == 0 && mk && c0 >= 0) atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(mk)));
-        } else if (acc) {
-          atomicAdd(&bacc[c], 1ull);
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int c = live[r] ? cs[r] : -1;
+          const int c0 = __shfl(c, 0);
+          if (__ballot(c != c0 && c >= 0) == 0) {
+            const uint64_t mk = __ballot(acc[r]);
+            if (lane_id() == 0 && mk && c0 >= 0) atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(mk)));
+          } else if (acc[r]) {
+            atomicAdd(&bacc[c], 1ull);
+          }
         }
       }
-      if (!grid_barrier(a.sync)) return false;
+      // between the classes only the spins change (coherent accesses); the phase ends
+      // with a full barrier
+      const bool last = s + 1 == a.nsw_max && cc + 1 == qmax;
+      if (!(last ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
       mark(a.trace, 1000 + cc);
     }
   }
-  for (int c = threadIdx.x; c < a.n_chains; c += kBlock)
+  for (int c = tid; c < a.n_chains; c += kBlock)
     if (bacc[c]) atomicAdd(&a.st[c].accepted, bacc[c]);
   if (blockIdx.x == 0)
-    for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
+    for (int c = tid; c < a.n_chains; c += kBlock) {
       const int nsw = a.nsw_override >= 0 ? a.nsw_override : a.cd[c].n_sw;
       a.st[c].attempts += static_cast<unsigned long long>(a.cd[c].N) * static_cast<unsigned long long>(nsw);
     }
@@ -939,6 +1362,7 @@ __device__ bool phase_sweep(const StepArgs& a) {
 // a complete graph (and colouring) is there.
 template <uint32_t phases>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
+  __shared__ PhaseLds lds;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if constexpr ((phases & PH_SWITCH) != 0) {
@@ -974,8 +1398,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     if (lead) a.sync->graph_valid = 1;
   }
   if constexpr ((phases & PH_COLOR) != 0) {
-    __shared__ KwChain kc[SCO_MAXCHAINS];
-    __shared__ int s_tiles;
+    __shared__ KwShared ks;
     if constexpr ((phases & PH_SWITCH) == 0) {
       // a separate colouring needs a completed switching (every block reads the
       // same word, written by an earlier launch)
@@ -986,11 +1409,11 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
       if (lead) a.sync->color_valid = 0;
     }
     mark(a.trace, 10);
-    const int ntiles = kw_setup(a, kc, &s_tiles);
-    phase_kw_local(a, kc, ntiles);
+    kw_setup(a, ks);
+    phase_kw_local(a, ks, lds.tile);
     mark(a.trace, 11);
     if (!grid_barrier(a.sync)) return;
-    if (!phase_kw_global(a, kc)) return;
+    if (!phase_kw_global(a, ks, lds.list)) return;
     mark(a.trace, 12);
     if (!grid_barrier(a.sync)) return;
     mark(a.trace, 13);
@@ -1004,7 +1427,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
       }
     }
     mark(a.trace, 20);
-    if (!phase_sweep(a)) return;
+    if (!phase_sweep(a, lds.list)) return;
     mark(a.trace, 21);
   }
 }
@@ -1016,8 +1439,8 @@ extern "C" __global__ void __launch_bounds__(kBlock)
     k_obs_basic(const ChainDesc* __restrict__ cd, const int32_t* __restrict__ chunk_chain,
                 const int8_t* __restrict__ spin, const uint16_t* __restrict__ color,
                 unsigned long long* __restrict__ out, unsigned* __restrict__ used, int64_t G) {
-  __shared__ unsigned s_used[SCO_MAXQ / 32];
-  if (threadIdx.x < SCO_MAXQ / 32) s_used[threadIdx.x] = 0;
+  __shared__ unsigned s_used[SCO_QWORDS];
+  if (threadIdx.x < SCO_QWORDS) s_used[threadIdx.x] = 0;
   __syncthreads();
   const int64_t g = gtid();
   const int c = chunk_chain[blockIdx.x];
@@ -1044,8 +1467,8 @@ extern "C" __global__ void __launch_bounds__(kBlock)
     atomicAdd(&out[2 * c], static_cast<unsigned long long>(m));
     atomicAdd(&out[2 * c + 1], static_cast<unsigned long long>(ex));
   }
-  if (threadIdx.x < SCO_MAXQ / 32 && s_used[threadIdx.x])
-    atomicOr(&used[c * (SCO_MAXQ / 32) + threadIdx.x], s_used[threadIdx.x]);
+  if (threadIdx.x < SCO_QWORDS && s_used[threadIdx.x])
+    atomicOr(&used[c * SCO_QWORDS + threadIdx.x], s_used[threadIdx.x]);
 }
 
 // Spins of one chain as bit rows: bit x of row y set when s(x, y) = -1; W words a row.
