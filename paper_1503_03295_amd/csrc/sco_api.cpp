@@ -389,6 +389,10 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
     d.neg_beta = -beta;
     d.inv_L = 1.0 / p.L;
     d.inv_rate = p.T / (p.kappa + 1.0);
+    d.inv_rate32 = static_cast<float>(d.inv_rate);
+    d.neg_beta32 = static_cast<float>(-beta);
+    d.twoJ32 = static_cast<float>(d.twoJ);
+    d.pad32 = 0.0f;
     for (int k = -4; k <= 4; ++k) {
       const double dE = (2.0 * p.J) * static_cast<double>(k);
       d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;

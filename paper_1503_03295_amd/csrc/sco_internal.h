@@ -37,6 +37,7 @@ struct ChainDesc {
   double C_top, guide_inv; // C_{K-1}, NB / C_top
   double twoJ, beta, inv_rate, neg_beta, inv_L;
   double pacc[9];          // exchange-only flips: index s_v * nn + 4; >= 1 means always accept
+  float inv_rate32, neg_beta32, twoJ32, pad32;  // FP32 copies (precision 1)
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
 };

@@ -277,10 +277,20 @@ struct ColorSet {
   uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
   __device__ __forceinline__ void add(int c) {
     const uint64_t b = 1ull << (c & 63);
-    if (c < 64) w0 |= b;
-    else if (c < 128) w1 |= b;
-    else if (c < 192) w2 |= b;
-    else w3 |= b;
+    const int h = (c >> 6) & 3;
+    w0 |= h == 0 ? b : 0ull;
+    w1 |= h == 1 ? b : 0ull;
+    w2 |= h == 2 ? b : 0ull;
+    w3 |= h == 3 ? b : 0ull;
+  }
+  // adds c when `on` (no branch)
+  __device__ __forceinline__ void add_if(bool on, int c) {
+    const uint64_t b = on ? 1ull << (c & 63) : 0ull;
+    const int h = (c >> 6) & 3;
+    w0 |= h == 0 ? b : 0ull;
+    w1 |= h == 1 ? b : 0ull;
+    w2 |= h == 2 ? b : 0ull;
+    w3 |= h == 3 ? b : 0ull;
   }
   // smallest colour not in the set (256 when all are taken)
   __device__ __forceinline__ int first_free() const {
@@ -394,11 +404,32 @@ __device__ __forceinline__ bool owner_take(const StepArgs& a, Owner& o, int& nex
   return false;
 }
 
+// First table index m > pos with C_m >= target (guide-table bracket, then binary
+// search over the FP64 cumulative couplings).
+__device__ __forceinline__ int table_search(const ChainDesc& d, double target, int pos) {
+  const double* __restrict__ C = d.C;
+  const int K = d.K, NB = d.nguide;
+  int b = static_cast<int>(target * d.guide_inv);
+  b = b < 0 ? 0 : (b > NB ? NB : b);
+  int lo = d.guide[b > 0 ? b - 1 : 0];
+  int hi = (b + 2 <= NB) ? d.guide[b + 2] : K - 1;
+  lo = lo > pos + 1 ? lo : pos + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 // One draw of a live owner: the next candidate (j, m) and whether it survives.  The
-// owner ends when the target passes C_top or the table is exhausted.
+// owner ends when the target passes C_top or the table is exhausted.  With precision
+// 1 the exponential gap is computed in FP32; the FP64 outcome is certain unless the
+// target lies within `tol` of C_top or of the table values it was compared with, and
+// then the gap is recomputed in FP64 (counted in `rechecks`).
 __device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, int& m) {
   const ChainDesc& d = a.cd[o.c];
-  const int K = d.K, NB = d.nguide;
+  const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
     o.live = false;
     return false;
@@ -415,23 +446,33 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, 
     whi = o.shi;
   }
   const double u1 = unit52(wlo, whi);
-  const double target = o.Cpos + (-log(u1)) * d.inv_rate;
-  if (target > d.C_top) {
-    o.live = false;
-    return false;
-  }
   const double* __restrict__ C = d.C;
-  int b = static_cast<int>(target * d.guide_inv);
-  b = b < 0 ? 0 : (b > NB ? NB : b);
-  int lo = d.guide[b > 0 ? b - 1 : 0];
-  int hi = (b + 2 <= NB) ? d.guide[b + 2] : K - 1;
-  lo = lo > o.pos + 1 ? lo : o.pos + 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (C[mid] >= target) hi = mid;
-    else lo = mid + 1;
+  bool done = false;
+  if (d.precision == 1) {
+    // -log u rounded through FP32 (u to float: 2^-24 relative; logf: about one ulp;
+    // the product: two roundings) stays within inv_rate (2^-24 + 2^-22 E) of the exact
+    // gap; tol takes four times that, plus the rounding of the FP64 sums.
+    const float E = -logf(static_cast<float>(u1));
+    const double target = o.Cpos + static_cast<double>(E * d.inv_rate32);
+    const double tol = static_cast<double>(d.inv_rate32) * (static_cast<double>(E) + 1.0) * 0x1p-20 + target * 0x1p-50;
+    if (target - tol > d.C_top) {
+      o.live = false;
+      return false;
+    }
+    if (target + tol <= d.C_top) {
+      m = table_search(d, target, o.pos);
+      done = C[m] >= target + tol && (m == o.pos + 1 || C[m - 1] < target - tol);
+    }
+    if (!done) atomicAdd(&a.st[o.c].rechecks, 1ull);  // rare: one atomic each
   }
-  m = lo;
+  if (!done) {
+    const double target = o.Cpos + (-log(u1)) * d.inv_rate;
+    if (target > d.C_top) {
+      o.live = false;
+      return false;
+    }
+    m = table_search(d, target, o.pos);
+  }
   const uint32_t p = d.hd[m];
   const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
   j = partner_of(o.x, o.y, dx, dy, d.L, d.periodic);
@@ -772,8 +813,7 @@ constexpr int kAdjCap = 16384;
 // LDS of the colouring and sweep phases: the tile arrays of the local levels, or the
 // bucket list of a block (block-local offsets) in the global levels and the sweeps.
 struct TileLds {
-  uint8_t col[SCO_TILE_MAX];        // current colour
-  uint8_t rho[SCO_TILE_MAX];        // round of the decision (0: undecided)
+  uint16_t cr[SCO_TILE_MAX];        // current colour | round of the decision << 8 (0: undecided)
   uint16_t list[SCO_TILE_MAX / 2];  // pending sites bucketed by colour
   uint16_t aoff[SCO_TILE_MAX + 1];  // in-tile bond list of site i: [aoff[i], aoff[i+1])
   uint16_t adj[kAdjCap];
@@ -788,8 +828,7 @@ union PhaseLds {
 // so the same-group neighbours of a tile site are inside the tile; the tile's
 // in-tile bonds are staged once, so a level touches global memory only at its end.
 __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared& ks, TileLds& tl) {
-  uint8_t* const t_col = tl.col;
-  uint8_t* const t_rho = tl.rho;
+  uint16_t* const t_cr = tl.cr;
   uint16_t* const t_list = tl.list;
   uint16_t* const t_aoff = tl.aoff;
   uint16_t* const t_adj = tl.adj;
@@ -812,7 +851,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     // half-group sizes are exact multiply-highs
     const uint32_t mq = magic16(static_cast<uint32_t>(q)), mL = magic16(static_cast<uint32_t>(L));
     const int y0 = fdiv(v0, K.inv_L), x0 = v0 - y0 * L;
-    for (int i = threadIdx.x; i < n; i += kBlock) t_col[i] = static_cast<uint8_t>(i - div16(i, mq) * q);
+    for (int i = threadIdx.x; i < n; i += kBlock) t_cr[i] = static_cast<uint16_t>(i - div16(i, mq) * q);
     if (P > 0) {
       // in-tile partner counts, then offsets (block scan), then the partners in row order
       for (int i = threadIdx.x; i < n; i += kBlock) {
@@ -871,7 +910,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       __syncthreads();
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
-        atomicAdd(&t_off[t_col[(2 * j + 1) * H + (k - j * H)] + 1], 1);
+        atomicAdd(&t_off[(t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF) + 1], 1);
       }
       __syncthreads();
       if (wave == 0) {  // exclusive prefix of the q <= 255 counts, four per lane
@@ -901,9 +940,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
         const int i = (2 * j + 1) * H + (k - j * H);
-        const int cc = t_col[i];
+        const int cc = t_cr[i] & 0xFF;
         t_list[t_off[cc] + atomicAdd(&t_fill[cc], 1)] = static_cast<uint16_t>(i);
-        t_rho[i] = 0;
+        t_cr[i] = static_cast<uint16_t>(cc);  // undecided at this level
       }
       __syncthreads();
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 80 + p);
@@ -914,24 +953,25 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
           const int grp = div16(i, mq) >> p;
           ColorSet taken;
           int rmax = 0;
-          // neighbour j (tile index): same group only; a pending one counts once decided
+          // neighbour j (tile index, -1 for none): same group only; a pending one
+          // counts once decided.  Branch-free, so the LDS reads of all neighbours are
+          // issued together.
           auto visit = [&](int j) {
-            if (j < 0 || j >= n) return;  // outside the tile: another group
-            const int gj = div16(j, mq);
-            if ((gj >> p) != grp) return;
-            if ((gj >> (p - 1)) & 1) {
-              const int rj = t_rho[j];
-              if (rj == 0) return;  // pending, undecided: a smaller colour
-              rmax = max(rmax, rj);
-            }
-            taken.add(t_col[j]);
+            const bool in = j >= 0 && j < n;  // outside the tile: another group
+            const int jj = in ? j : i;
+            const int w = t_cr[jj];
+            const int gj = div16(jj, mq);
+            const bool pend = (gj >> (p - 1)) & 1;
+            const int rj = w >> 8;
+            const bool on = in && (gj >> p) == grp && (!pend || rj != 0);
+            rmax = max(rmax, on && pend ? rj : 0);
+            taken.add_if(on, w & 0xFF);
           };
           const int t = x0 + i, dy = div16(t, mL);
           int nb[4];
           nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (nb[u] >= 0) visit(nb[u] - v0);
+          for (int u = 0; u < 4; ++u) visit(nb[u] >= 0 ? nb[u] - v0 : -1);
           const int e0 = t_aoff[i], e1 = t_aoff[i + 1];
           if (e1 <= kAdjCap) {
             for (int e = e0; e < e1; ++e) visit(t_adj[e]);
@@ -944,8 +984,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
             set_flag(a.sync, SCO_FLAG_PALETTE);
             nc = q - 1;
           }
-          t_col[i] = static_cast<uint8_t>(nc);
-          t_rho[i] = static_cast<uint8_t>(rmax + 1);
+          t_cr[i] = static_cast<uint16_t>(nc | ((rmax + 1) << 8));
           tmax = max(tmax, rmax + 1);
         }
         tmax = wave_max(tmax);
@@ -957,8 +996,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     }
     const uint32_t tag = static_cast<uint32_t>(P) << 18;
     for (int i = threadIdx.x; i < n; i += kBlock) {
-      a.color[gt0 + i] = t_col[i];
-      a.kw_word[gt0 + i] = tag | t_col[i];
+      const uint32_t col = t_cr[i] & 0xFFu;
+      a.color[gt0 + i] = static_cast<uint16_t>(col);
+      a.kw_word[gt0 + i] = tag | col;
     }
     __syncthreads();
   }
@@ -1305,21 +1345,58 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
               }
             }
           } else {
-            double h = d.twoJ * static_cast<double>(nsum[r]);
-            for (int t = q0[r]; t < q1[r]; ++t) {
-              const double dm = d.delta[a.attr[t]];
-              h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+            bool done = false;
+            if (d.precision == 1) {
+              // FP32 local field.  Each term carries the rounding of delta to FP32 and
+              // each addition one more, so |dE32 - dE| <= 2 (n + 1) 2^-24 sum|terms|;
+              // errE takes twice that.  A decision within errE of dE = 0, or with u
+              // within errP of p, is recomputed in FP64 (counted in `rechecks`).
+              float h = d.twoJ32 * static_cast<float>(nsum[r]);
+              float mag = fabsf(h);
+              for (int t = q0[r]; t < q1[r]; ++t) {
+                const float dm = d.delta32[a.attr[t]];
+                h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+                mag += fabsf(dm);
+              }
+              const float dE = sv[r] > 0 ? h : -h;
+              const float errE = mag * static_cast<float>(q1[r] - q0[r] + 3) * 0x1p-22f;
+              if (dE < -errE) {
+                acc[r] = done = true;
+              } else if (dE > errE) {
+                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                      d.seed, d.chain_id);
+                const double u = unit52(w.x, w.y);
+                const float x = d.neg_beta32 * dE;
+                const float pr = expf(x);
+                // expf: about one ulp; beta and the product: one rounding each; the
+                // field: errE
+                const double errP =
+                    static_cast<double>(pr) * (static_cast<double>(-d.neg_beta32) * errE * 1.01 + fabs(x) * 0x1p-21 + 0x1p-21) +
+                    0x1p-126;
+                if (fabs(u - static_cast<double>(pr)) > errP) {
+                  acc[r] = u < static_cast<double>(pr);
+                  done = true;
+                }
+              }
+              if (!done) atomicAdd(&a.st[c].rechecks, 1ull);
             }
-            const double dE = sv[r] > 0 ? h : -h;
-            if (dE <= 0.0) {
-              acc[r] = true;
-            } else {
-              const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
-                                    d.seed, d.chain_id);
-              const double u = unit52(w.x, w.y);
-              const double pr = exp(d.neg_beta * dE);
-              if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
-              acc[r] = u < pr;
+            if (!done) {
+              double h = d.twoJ * static_cast<double>(nsum[r]);
+              for (int t = q0[r]; t < q1[r]; ++t) {
+                const double dm = d.delta[a.attr[t]];
+                h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+              }
+              const double dE = sv[r] > 0 ? h : -h;
+              if (dE <= 0.0) {
+                acc[r] = true;
+              } else {
+                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                      d.seed, d.chain_id);
+                const double u = unit52(w.x, w.y);
+                const double pr = exp(d.neg_beta * dE);
+                if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
+                acc[r] = u < pr;
+              }
             }
           }
           if (acc[r]) st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));

@@ -121,3 +121,64 @@ def test_large_lattice_first_steps():
     for k in ("M", "n_edges", "delta_union", "q", "colors_used", "kw_levels", "kw_rounds"):
         assert go[k] == ro[k], k
     assert abs(go["E"] - ro["E"]) <= 1e-12 * abs(ro["E"])
+
+
+@pytest.mark.parametrize("kappa", [1.5, 2.0])
+def test_mixed_precision_matches_fp64_oracle(kappa):
+    """FP32 gaps and local fields with FP64 recheck: the same chain as the FP64
+    oracle, bit for bit (L=256 periodic, three temperatures)."""
+    params = [workloads.chain(256, True, T, kappa, chain_id=i, precision=1)
+              for i, T in enumerate((0.8, 1.2, 2.0))]
+    log(f"mixed precision kappa={kappa}")
+    out = run_parity(params, 30, graph_every=5, obs_every=15)
+    obs = out["gpu"].observables()
+    rechecks = sum(o["rechecks"] for o in obs)
+    attempts = sum(o["attempts"] for o in obs)
+    log(f"  rechecks {rechecks} of {attempts} attempts (+ switching draws)")
+    assert rechecks > 0, "the FP64 recheck path was never taken"
+
+
+def test_mixed_precision_equals_fp64_gpu_chain():
+    """precision 1 and precision 0 contexts of the same chain stay identical."""
+    from paper_1503_03295_amd import SCO
+
+    p0 = workloads.chain(512, True, 1.1, 2.0, n_sw=3)
+    p1 = dict(p0, precision=1)
+    a = SCO([gpu_params(p0)], device="cuda:0")
+    b = SCO([gpu_params(p1)], device="cuda:0")
+    log("mixed precision vs fp64 on the GPU, L=512")
+    for t in range(25):
+        a.step(t)
+        b.step(t)
+        np.testing.assert_array_equal(a.spins(0), b.spins(0), err_msg=f"step {t}")
+    ra, rb = a.graph(0), b.graph(0)
+    for x, y in zip(ra, rb):
+        np.testing.assert_array_equal(x, y)
+    assert a.observables()[0]["rechecks"] == 0
+    assert b.observables()[0]["rechecks"] > 0
+
+
+def test_batched_64_chains_sampled_against_oracle():
+    """The 64-chain batch (L from 64 to 1024, T in [0.8, 2.5]) in one context: two
+    steps, every chain up to L=512 and one L=1024 chain checked against the oracle."""
+    from paper_1503_03295_amd import SCO
+
+    params = workloads.batched()
+    gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
+    sample = [c for c, p in enumerate(params) if p["L"] <= 512]
+    sample += [next(c for c, p in enumerate(params) if p["L"] == 1024)]
+    log(f"batched: {len(params)} chains, {sum(p['L'] ** 2 for p in params)} spins; checking {len(sample)}")
+    refs = {c: oracle.OracleChain(oracle_params(params[c])) for c in sample}
+    for t in range(2):
+        gpu.step(t)
+        for c, r in refs.items():
+            r.step(t)
+            if not np.array_equal(gpu.spins(c), r.spins):
+                ties = r.observables(dipolar="none")["near_ties"]
+                assert ties > 0, f"chain {c} (L={params[c]['L']}) step {t} differs"
+                r.spins = gpu.spins(c)
+    go = gpu.observables()
+    for c, r in refs.items():
+        ro = r.observables(dipolar="none")
+        for k in ("M", "n_edges", "delta_union", "q", "kw_levels", "kw_rounds"):
+            assert go[c][k] == ro[k], (c, k)
