@@ -13,7 +13,7 @@ EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
-    "sco_strerror",
+    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune",
 ]
 
 

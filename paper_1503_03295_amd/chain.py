@@ -144,6 +144,21 @@ class SCO:
                                    ptr(th), ptr(de)), "sco_get_tables")
         return {"dx": dx, "dy": dy, "J": J, "C": C, "theta": th, "delta": de}
 
+    # -- schedule (never changes results)
+    def set_schedule(self, blocks: int = 0, tile_limit: int = 0) -> None:
+        check(lib().sco_set_schedule(self._h, int(blocks), int(tile_limit)), "sco_set_schedule")
+
+    def schedule(self) -> tuple[int, int]:
+        b, t = ctypes.c_int(), ctypes.c_int()
+        check(lib().sco_get_schedule(self._h, ctypes.byref(b), ctypes.byref(t)), "sco_get_schedule")
+        return b.value, t.value
+
+    def autotune(self, trial_steps: int = 3) -> dict:
+        b, t, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+        check(lib().sco_autotune(self._h, int(trial_steps), ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)),
+              "sco_autotune")
+        return {"blocks": b.value, "tile_limit": t.value, "ms_per_step": ms.value}
+
     def phase_times(self) -> tuple[float, float, float]:
         out = (ctypes.c_float * 3)()
         check(lib().sco_phase_times(self._h, out), "sco_phase_times")

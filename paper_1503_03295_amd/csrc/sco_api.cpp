@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -51,6 +52,7 @@ struct Layout {
   size_t off_sync = 0, off_cd = 0, off_st = 0, off_chunk = 0, off_srcbase = 0;
   size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0;
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
+  size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_ts = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
@@ -125,6 +127,8 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_trace = take(sizeof(unsigned long long) * SCO_TRACE_SLOTS);
   lay.ntiles = G / (16 * SCO_CHUNK) + 2;
   lay.off_ts = take(sizeof(unsigned long long) * lay.ntiles);
+  lay.off_spin_bak = take(G);  // autotuning trials restore the chain from here
+  lay.off_st_bak = take(sizeof(ChainState) * n);
   lay.off_obs = take(sizeof(unsigned long long) * 2 * n);
   lay.off_used = take(sizeof(uint32_t) * SCO_QWORDS * n);
   int maxbits = 0;
@@ -179,7 +183,8 @@ struct sco_ctx {
   std::vector<std::vector<double>> theta, delta;   // per chain (empty when hard)
   std::vector<ChainDesc> cd;                       // host copy of the descriptors
   StepArgs args{};
-  int blocks = 0;
+  int blocks = 0, max_blocks = 0;  // grid of the step kernel (schedule), co-resident limit
+  int launched_blocks = 0;         // grid of the last launch (its barrier counters)
   int nsw_max = 0;
   int graph_state = 0;  // 0 no bond graph yet, 1 switched, 2 switched and coloured
   uint32_t epoch = 0;
@@ -232,11 +237,24 @@ int consume_flags(sco_ctx* c) {
   return SCO_EINTERNAL;
 }
 
+// Launches `phases` for SCO step `step`.  Each launch gets its own 24-bit epoch for
+// the scan tile states; before the epochs would wrap, the tile states are reset to a
+// value that no epoch matches.
 int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
   if (step > 0xFFFFFFFFull) return SCO_EINVAL;
+  if (c->epoch + 1u >= 0xFFFFFFu) {
+    HIP_TRY(hipMemsetAsync(at<unsigned long long>(c, c->lay.off_ts), 0xFF,
+                           sizeof(unsigned long long) * c->lay.ntiles, c->stream));
+    c->epoch = 0;
+  }
+  if (c->blocks != c->launched_blocks) {
+    // the barrier counters count arrivals in groups sized by the grid: start them
+    // afresh for another grid size (stream-ordered: no launch is running)
+    HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, offsetof(SyncWords, flags), c->stream));
+    c->launched_blocks = c->blocks;
+  }
   c->args.step = static_cast<uint32_t>(step);
-  c->args.epoch = ++c->epoch & 0xFFFFFFu;
-  if (c->args.epoch == 0xFFFFFFu) c->args.epoch = c->epoch = 1;
+  c->args.epoch = ++c->epoch;
   if (c->trace_on) {
     c->args.trace = at<unsigned long long>(c, c->lay.off_trace);
     HIP_TRY(hipMemsetAsync(c->args.trace, 0, sizeof(unsigned long long), c->stream));
@@ -392,7 +410,7 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
     d.inv_rate32 = static_cast<float>(d.inv_rate);
     d.neg_beta32 = static_cast<float>(-beta);
     d.twoJ32 = static_cast<float>(d.twoJ);
-    d.pad32 = 0.0f;
+    d.twoJ32_exact = static_cast<double>(d.twoJ32) == d.twoJ ? 1 : 0;
     for (int k = -4; k <= 4; ++k) {
       const double dE = (2.0 * p.J) * static_cast<double>(k);
       d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
@@ -480,7 +498,9 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   a.cap_und = L.cap_und;
   const int maxb = sco_dev::step_max_blocks();
   if (maxb <= 0) return fail(SCO_EHIP);
-  c->blocks = std::min(maxb, SCO_MAX_BLOCKS);
+  c->max_blocks = std::min(maxb, SCO_MAX_BLOCKS);
+  c->blocks = c->max_blocks;
+  c->args.tile_limit = SCO_TILE_MAX;
   {
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -538,6 +558,79 @@ int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
     if (rc) return rc;
     c->graph_state = 2;
   }
+  return SCO_OK;
+}
+
+int sco_set_schedule(sco_ctx* c, int blocks, int tile_limit) {
+  if (!c) return SCO_EINVAL;
+  if (blocks == 0) blocks = c->max_blocks;
+  if (tile_limit == 0) tile_limit = SCO_TILE_MAX;
+  if (blocks < 1 || blocks > c->max_blocks || tile_limit < 64 || tile_limit > SCO_TILE_MAX) return SCO_EINVAL;
+  c->blocks = blocks;
+  c->args.tile_limit = tile_limit;
+  return SCO_OK;
+}
+
+int sco_get_schedule(sco_ctx* c, int* blocks, int* tile_limit) {
+  if (!c) return SCO_EINVAL;
+  if (blocks) *blocks = c->blocks;
+  if (tile_limit) *tile_limit = c->args.tile_limit;
+  return SCO_OK;
+}
+
+int sco_autotune(sco_ctx* c, int trial_steps, int* blocks, int* tile_limit, float* ms_per_step) {
+  if (!c || trial_steps < 1 || trial_steps > 1000) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  if (fr) return fr;
+  const Layout& L = c->lay;
+  // the chain's state before the trials: spins and counters
+  HIP_TRY(hipMemcpyAsync(at<int8_t>(c, L.off_spin_bak), at<int8_t>(c, L.off_spin), L.G, hipMemcpyDeviceToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(at<ChainState>(c, L.off_st_bak), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n,
+                         hipMemcpyDeviceToDevice, c->stream));
+  const int cand_blocks[3] = {c->max_blocks, (c->max_blocks * 3) / 4, c->max_blocks / 2};
+  const int cand_tiles[3] = {SCO_TILE_MAX, SCO_TILE_MAX / 2, SCO_TILE_MAX / 4};
+  float best = -1.0f;
+  int best_b = c->blocks, best_t = c->args.tile_limit;
+  for (int bi = 0; bi < 3; ++bi)
+    for (int ti = 0; ti < 3; ++ti) {
+      const int b = cand_blocks[bi];
+      if (b < 1 || (bi > 0 && b == cand_blocks[bi - 1])) continue;
+      c->blocks = b;
+      c->args.tile_limit = cand_tiles[ti];
+      // trial steps from the saved state, with step counters no chain uses
+      HIP_TRY(hipMemcpyAsync(at<int8_t>(c, L.off_spin), at<int8_t>(c, L.off_spin_bak), L.G,
+                             hipMemcpyDeviceToDevice, c->stream));
+      int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, 0xFFFFFF00u, -1);  // warm-up
+      HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+      for (int s = 0; s < trial_steps && rc == SCO_OK; ++s)
+        rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, 0xFFFFFF01u + static_cast<uint32_t>(s), -1);
+      HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+      if (rc) return rc;
+      HIP_TRY(hipEventSynchronize(c->ev[1]));
+      const int f = consume_flags(c);
+      if (f) return f;
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+      ms /= static_cast<float>(trial_steps);
+      if (best < 0.f || ms < best) {
+        best = ms;
+        best_b = b;
+        best_t = cand_tiles[ti];
+      }
+    }
+  c->blocks = best_b;
+  c->args.tile_limit = best_t;
+  HIP_TRY(hipMemcpyAsync(at<int8_t>(c, L.off_spin), at<int8_t>(c, L.off_spin_bak), L.G, hipMemcpyDeviceToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(at<ChainState>(c, L.off_st), at<ChainState>(c, L.off_st_bak), sizeof(ChainState) * c->n,
+                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  // the trials left their own bond graph: a colouring or sweep needs a new switching
+  c->graph_state = 0;
+  if (blocks) *blocks = best_b;
+  if (tile_limit) *tile_limit = best_t;
+  if (ms_per_step) *ms_per_step = best;
   return SCO_OK;
 }
 

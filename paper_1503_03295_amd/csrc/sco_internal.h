@@ -37,7 +37,8 @@ struct ChainDesc {
   double C_top, guide_inv; // C_{K-1}, NB / C_top
   double twoJ, beta, inv_rate, neg_beta, inv_L;
   double pacc[9];          // exchange-only flips: index s_v * nn + 4; >= 1 means always accept
-  float inv_rate32, neg_beta32, twoJ32, pad32;  // FP32 copies (precision 1)
+  float inv_rate32, neg_beta32, twoJ32;  // FP32 copies (precision 1)
+  int32_t twoJ32_exact;                   // 2J is exact in FP32: bond-free fields are exact
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
 };
@@ -88,6 +89,7 @@ struct StepArgs {
   int32_t nsw_max;
   uint32_t step;
   uint32_t epoch;         // launch counter (tags the scan tile states)
+  int32_t tile_limit;     // sites of a KW tile, <= SCO_TILE_MAX (a schedule choice)
 };
 
 #define SCO_TRACE_SLOTS 512

@@ -272,6 +272,16 @@ __device__ __forceinline__ void wave_max_to(int* per_chain, int c, int val) {
   }
 }
 
+// A CSR row [r0, r1) inside the edge arrays.  Anything else, which only a launch
+// that broke off could leave, raises SCO_FLAG_STATE and reads as an empty row.
+__device__ __forceinline__ void row_checked(const StepArgs& a, int& r0, int& r1) {
+  const int cap2 = 2 * static_cast<int>(a.cap_und);
+  if (r0 < 0 || r1 < r0 || r1 > cap2) {
+    set_flag(a.sync, SCO_FLAG_STATE);
+    r0 = r1 = 0;
+  }
+}
+
 // 256-bit colour set without dynamic register indexing
 struct ColorSet {
   uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
@@ -427,7 +437,7 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, double target, i
 // 1 the exponential gap is computed in FP32; the FP64 outcome is certain unless the
 // target lies within `tol` of C_top or of the table values it was compared with, and
 // then the gap is recomputed in FP64 (counted in `rechecks`).
-__device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, int& m) {
+__device__ __forceinline__ bool owner_draw(const StepArgs& a, uint32_t step, Owner& o, int& j, int& m) {
   const ChainDesc& d = a.cd[o.c];
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -436,7 +446,7 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, 
   }
   uint32_t wlo, whi;
   if ((o.k & 1u) == 0) {
-    const W4 r = philox10(a.step, static_cast<uint32_t>(o.v), o.k >> 1, SCO_TAG_SW, d.seed, d.chain_id);
+    const W4 r = philox10(step, static_cast<uint32_t>(o.v), o.k >> 1, SCO_TAG_SW, d.seed, d.chain_id);
     wlo = r.x;
     whi = r.y;
     o.slo = r.z;
@@ -480,7 +490,7 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, 
   if (j >= 0) {
     found = o.si != a.spin[d.vbase + j];
     if (!found && !d.hard) {
-      const W4 t = philox10(a.step, static_cast<uint32_t>(o.v), o.k, SCO_TAG_TH, d.seed, d.chain_id);
+      const W4 t = philox10(step, static_cast<uint32_t>(o.v), o.k, SCO_TAG_TH, d.seed, d.chain_id);
       found = unit52(t.x, t.y) < d.theta[m];
     }
   }
@@ -502,7 +512,7 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, Owner& o, int& j, 
 // range in flight and starts the next one as soon as one ends, so a wave is not held
 // by its slowest owner.  Survivors go to the block's region (one LDS atomic per wave
 // and append); its count is written to the entry of the range's first chunk.
-__device__ __forceinline__ void phase_switch(const StepArgs& a) {
+__device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
   __shared__ uint32_t s_count;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
@@ -540,8 +550,8 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a) {
   owner_take(a, B, next, ch1);
   while (__ballot(A.live || B.live) != 0) {
     int jA = -1, mA = 0, jB = -1, mB = 0;
-    const bool fA = A.live && owner_draw(a, A, jA, mA);
-    const bool fB = B.live && owner_draw(a, B, jB, mB);
+    const bool fA = A.live && owner_draw(a, step, A, jA, mA);
+    const bool fB = B.live && owner_draw(a, step, B, jB, mB);
     append(fA, A.g, A.c, jA, mA);
     append(fB, B.g, B.c, jB, mB);
     if (!A.live) owner_take(a, A, next, ch1);
@@ -675,7 +685,8 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
     const int v = static_cast<int>(g - d.vbase);
     int udeg = 0, rowlen = 0;
     if (v < d.N) {
-      const int r0 = a.row_ptr[g], r1 = a.row_ptr[g + 1];
+      int r0 = a.row_ptr[g], r1 = a.row_ptr[g + 1];
+      row_checked(a, r0, r1);
       rowlen = r1 - r0;
       int32_t* __restrict__ col = a.col;
       int32_t* __restrict__ attr = a.attr;
@@ -724,7 +735,8 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
 // rho(v) = 1 + max rho over those larger neighbours; a level takes max rho rounds.
 //
 // Per chain: P = the levels whose groups (q 2^p sites, aligned) fit in one LDS tile
-// of T = q 2^P <= SCO_TILE_MAX sites; those run tile by tile entirely in LDS.  The
+// of T = q 2^P <= tile_limit (at most SCO_TILE_MAX) sites; those run tile by tile
+// entirely in LDS.  The
 // levels above P run over the whole site space with device-wide barriers between
 // colour classes, their pending sites spread evenly over the blocks.
 struct KwChain {
@@ -753,7 +765,7 @@ __device__ __forceinline__ void kw_setup(const StepArgs& a, KwShared& ks) {
     int M = 0;
     while ((1 << M) < groups) ++M;
     int P = 0;
-    while (P < M && (q << (P + 1)) <= SCO_TILE_MAX) ++P;
+    while (P < M && (q << (P + 1)) <= a.tile_limit) ++P;
     KwChain& k = ks.kc[c];
     k.q = q;
     k.M = M;
@@ -855,7 +867,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     if (P > 0) {
       // in-tile partner counts, then offsets (block scan), then the partners in row order
       for (int i = threadIdx.x; i < n; i += kBlock) {
-        const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        row_checked(a, r0, r1);
         int k = 0;
         for (int e = r0; e < r1; ++e) {
           const int j = a.col[e] - gt0;
@@ -891,7 +904,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         const int e_end = t_aoff[i + 1];
         if (e_end > kAdjCap) continue;  // read from global memory when needed
         int w = t_aoff[i];
-        const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+        row_checked(a, r0, r1);
         for (int e = r0; e < r1 && w < e_end; ++e) {
           const int j = a.col[e] - gt0;
           if (j >= 0 && j < n) t_adj[w++] = static_cast<uint16_t>(j);
@@ -976,7 +990,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
           if (e1 <= kAdjCap) {
             for (int e = e0; e < e1; ++e) visit(t_adj[e]);
           } else {
-            const int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+            int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+            row_checked(a, r0, r1);
             for (int e = r0; e < r1; ++e) visit(a.col[e] - gt0);
           }
           int nc = taken.first_free();
@@ -1138,6 +1153,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
               if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
             rb[r] = a.row_ptr[gs[r]];
             re[r] = a.row_ptr[gs[r] + 1];
+            row_checked(a, rb[r], re[r]);
           }
         }
         // the first two bond partners and their words
@@ -1226,7 +1242,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
 // acceptance is the table pacc.
 constexpr int kLocalChains = 4;  // chain descriptors of a block's range held in LDS
 
-__device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list) {
+__device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
   __shared__ int32_t bfill[SCO_MAXQ];
   __shared__ unsigned long long bacc[SCO_MAXCHAINS];  // accepted flips of the block per chain
@@ -1321,6 +1337,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
               sv[r] = ld_relaxed(&a.spin[gs[r]]);
               q0[r] = a.row_ptr[gs[r]];
               q1[r] = a.row_ptr[gs[r] + 1];
+              row_checked(a, q0[r], q1[r]);
             }
           }
         }
@@ -1339,7 +1356,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
               if (pa >= 1.0) {
                 acc[r] = true;
               } else {
-                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                       d.seed, d.chain_id);
                 acc[r] = unit52(w.x, w.y) < pa;
               }
@@ -1359,11 +1376,14 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
                 mag += fabsf(dm);
               }
               const float dE = sv[r] > 0 ? h : -h;
-              const float errE = mag * static_cast<float>(q1[r] - q0[r] + 3) * 0x1p-22f;
-              if (dE < -errE) {
+              // a bond-free field 2J nn is exact when 2J is (|nn| <= 4)
+              const float errE = (q1[r] == q0[r] && d.twoJ32_exact)
+                                     ? 0.0f
+                                     : mag * static_cast<float>(q1[r] - q0[r] + 3) * 0x1p-22f;
+              if (dE <= -errE) {
                 acc[r] = done = true;
               } else if (dE > errE) {
-                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                       d.seed, d.chain_id);
                 const double u = unit52(w.x, w.y);
                 const float x = d.neg_beta32 * dE;
@@ -1390,7 +1410,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
               if (dE <= 0.0) {
                 acc[r] = true;
               } else {
-                const W4 w = philox10(a.step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                       d.seed, d.chain_id);
                 const double u = unit52(w.x, w.y);
                 const double pr = exp(d.neg_beta * dE);
@@ -1438,8 +1458,8 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, int32_t* lds_list
 // graph; a launch without it checks that the words left by the earlier launches say
 // a complete graph (and colouring) is there.
 template <uint32_t phases>
-__global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
-  __shared__ PhaseLds lds;
+__device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, uint32_t epoch, PhaseLds& lds,
+                                          KwShared& ks) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if constexpr ((phases & PH_SWITCH) != 0) {
@@ -1457,31 +1477,30 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
       a.deg[g] = 0;
       a.fill[g] = 0;
     }
-    if (!grid_barrier(a.sync)) return;
+    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 1);
-    phase_switch(a);
+    phase_switch(a, step);
     mark(a.trace, 2);
-    if (!grid_barrier(a.sync)) return;
+    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
-    if (!scan_lookback(a.deg, a.G, a.row_ptr, a.scan_ts, a.epoch, a.sync)) return;
-    if (!grid_barrier(a.sync)) return;
+    if (!scan_lookback(a.deg, a.G, a.row_ptr, a.scan_ts, epoch, a.sync)) return false;
+    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 4);
     phase_scatter(a);
-    if (!grid_barrier(a.sync)) return;
+    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 5);
     phase_rowsort(a);
-    if (!grid_barrier(a.sync)) return;
+    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 6);
     if (lead) a.sync->graph_valid = 1;
   }
   if constexpr ((phases & PH_COLOR) != 0) {
-    __shared__ KwShared ks;
     if constexpr ((phases & PH_SWITCH) == 0) {
       // a separate colouring needs a completed switching (every block reads the
       // same word, written by an earlier launch)
       if (a.sync->graph_valid != 1) {
         if (lead) set_flag(a.sync, SCO_FLAG_STATE);
-        return;
+        return false;
       }
       if (lead) a.sync->color_valid = 0;
     }
@@ -1489,24 +1508,39 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     kw_setup(a, ks);
     phase_kw_local(a, ks, lds.tile);
     mark(a.trace, 11);
-    if (!grid_barrier(a.sync)) return;
-    if (!phase_kw_global(a, ks, lds.list)) return;
+    if (!grid_barrier(a.sync)) return false;
+    // the global levels end with a full barrier (none when every level ran in tiles)
+    if (!phase_kw_global(a, ks, lds.list)) return false;
     mark(a.trace, 12);
-    if (!grid_barrier(a.sync)) return;
-    mark(a.trace, 13);
     if (lead) a.sync->color_valid = 1;
   }
   if constexpr ((phases & PH_SWEEP) != 0) {
     if constexpr ((phases & PH_COLOR) == 0) {
       if (a.sync->color_valid != 1) {
         if (lead) set_flag(a.sync, SCO_FLAG_STATE);
-        return;
+        return false;
       }
     }
     mark(a.trace, 20);
-    if (!phase_sweep(a, lds.list)) return;
+    // the sweeps end with a full barrier, so the next step sees every spin
+    if (!phase_sweep(a, step, lds.list)) return false;
     mark(a.trace, 21);
   }
+  return true;
+}
+
+// Persistent kernel (cooperative launch: every block resident), one step of every
+// chain.  `phases` selects steps (1) switching + assembly, (2) colouring, (3) sweeps.
+// The switching part starts by clearing the degree and cursor arrays and the
+// per-chain counters of the graph; a launch without it checks that the words left by
+// the earlier launches say a complete graph (and colouring) is there.  (Looping over
+// several steps inside one launch was measured to push the fused kernel past its
+// register budget into spills, for a saving of a few microseconds per step.)
+template <uint32_t phases>
+__global__ void __launch_bounds__(kBlock) k_step(const StepArgs a) {
+  __shared__ PhaseLds lds;
+  __shared__ KwShared ks;
+  step_body<phases>(a, a.step, a.epoch, lds, ks);
 }
 
 // =================================================================== observables

@@ -182,3 +182,45 @@ def test_batched_64_chains_sampled_against_oracle():
         ro = r.observables(dipolar="none")
         for k in ("M", "n_edges", "delta_union", "q", "kw_levels", "kw_rounds"):
             assert go[c][k] == ro[k], (c, k)
+
+
+def test_schedules_give_identical_chains():
+    """Grid size and tile limit change the schedule only: the same spins, bond graph
+    and colours for every choice, and the autotuner restores the chain it timed on."""
+    from paper_1503_03295_amd import SCO
+
+    params = [workloads.chain(256, True, 1.2, 2.0, chain_id=0), workloads.chain(96, False, 0.9, 1.0, chain_id=1)]
+    ref = SCO([gpu_params(p) for p in params], device="cuda:0")
+    for t in range(4):
+        ref.step(t)
+    maxb, _ = ref.schedule()
+    log(f"schedules: co-resident blocks {maxb}")
+    for blocks, tile in ((maxb // 2, 16384), (maxb, 4096), (max(1, maxb // 3), 1024), (7, 64)):
+        g = SCO([gpu_params(p) for p in params], device="cuda:0")
+        g.set_schedule(blocks, tile)
+        assert g.schedule() == (blocks, tile)
+        for t in range(4):
+            g.step(t)
+        for c in range(len(params)):
+            np.testing.assert_array_equal(g.spins(c), ref.spins(c))
+            for x, y in zip(g.graph(c), ref.graph(c)):
+                np.testing.assert_array_equal(x, y)
+        obs_g, obs_r = g.observables(), ref.observables()
+        for og, orr in zip(obs_g, obs_r):
+            for k in ("M", "n_edges", "q", "kw_rounds", "accepted"):
+                assert og[k] == orr[k], (blocks, tile, k)
+    # the autotuner times trials and leaves the chain where it was
+    a = SCO([gpu_params(p) for p in params], device="cuda:0")
+    for t in range(2):
+        a.step(t)
+    before = [a.spins(c) for c in range(len(params))]
+    acc_before = [o["accepted"] for o in a.observables()]
+    choice = a.autotune(2)
+    log(f"  autotune: {choice}")
+    for c in range(len(params)):
+        np.testing.assert_array_equal(a.spins(c), before[c])
+    assert [o["accepted"] for o in a.observables()] == acc_before
+    for t in range(2, 4):
+        a.step(t)
+    for c in range(len(params)):
+        np.testing.assert_array_equal(a.spins(c), ref.spins(c))
