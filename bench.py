@@ -40,16 +40,78 @@ def expected_candidates(J, T, kappa):
     return float(np.sum(-np.expm1(-(kappa + 1.0) * J / T)))
 
 
-def phase_bytes(N, E, c, q, M, k_mean, hard, n_sw):
-    """Algorithmic bytes per step of each phase (the data each phase must touch
-    once; table look-ups excluded).  E: undirected surviving bonds; c: candidates
-    per owner; k_mean: mean surviving-bond degree."""
-    switch = N * (8 + 1 + c + 8 + 4) + E * (12 + 16 + 12 + 16 + 8 + 16 + 32)
-    per_pending = 4 + 4 + 8 + (4 + k_mean) * 8 + 4 * k_mean + 4
-    color = N * (6 + M * (6 + 0.5 * per_pending) + 8)
-    per_attempt = 4 + 1 + 4 + 8 + 0.3 + (0.0 if hard else k_mean * 17)
+def phase_bytes(N, E, c, M, P, k_mean, hard, n_sw, accept):
+    """Algorithmic bytes of one step, per phase: the data each phase must move once
+    (the displacement-table probes are cache-resident and not counted).
+      switch    per owner: its spin (1) + the partner spin of each candidate (c) +
+                its survivor count (4)
+      assembly  per site: degree scan read + write (8); per survivor s = E/N:
+                both directions (2 x 8) + cursor atomics (4) + row sort read/write (16)
+      colour    per pending site and level run over the whole lattice (M - P levels,
+                N/2 pending each): row_ptr (4) + bond partners (4k) + neighbour
+                words (4 + k) + the decision (2); the P levels held in LDS count once
+      sweep     per attempt: list entry (4) + own spin (1) + NN spins (4) + row_ptr (4)
+                + per bond: partner (4) + coupling (8 FP64, 4 FP32 when hard: 0) +
+                partner spin (1) + the accepted write (acceptance a)"""
+    s = E / N
+    switch = N * (1 + c + 4)
+    assembly = N * (8 + s * (16 + 4 + 16))
+    per_pending = 4 + 4 * k_mean + (4 + k_mean) + 2
+    colour = max(M - P, 0) * (N / 2) * per_pending + N * per_pending
+    per_attempt = 4 + 1 + 4 + 4 + (0.0 if hard else k_mean * (4 + 8 + 1)) + accept
     sweep = N * n_sw * per_attempt
-    return {"switch": switch, "color": color, "sweep": sweep}
+    return {"switch": switch + assembly, "color": colour, "sweep": sweep}
+
+
+def measured_traffic():
+    """HBM bytes per k_step<7u> launch from the committed rocprofv3 --pmc summary, or
+    None when the kernel sources have changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_step_L2304_traffic.md")
+    csrc = os.path.join(ROOT, "paper_1503_03295_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256(open(os.path.join(csrc, "sco_kernels.hip"), "rb").read() +
+                           open(os.path.join(csrc, "sco_internal.h"), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+    if fields.get("source_sha256", "").strip() != h:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def time_steps(sco, first, steps, torch):
+    """ms per step of `steps` full steps (HIP events on the library's stream)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sco.stream)
+    sco.run(first, steps)
+    e1.record(sco.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def workload_leg(name, params, steps, torch, SCO, ChainParams, autotune=True):
+    """One extra workload: spins, attempts/s and the chosen schedule."""
+    sco = SCO([ChainParams(**p) for p in params], device="cuda:0")
+    sched = sco.autotune(2) if autotune else None
+    sco.run(0, 2)
+    ms = time_steps(sco, 2, steps, torch)
+    obs = sco.observables()
+    spins = sum(p["L"] ** 2 for p in params)
+    attempts = sum(p["L"] ** 2 * p["n_sw"] for p in params)
+    out = {"chains": len(params), "spins": spins, "steps": steps, "ms_per_step": ms,
+           "attempts_per_s": attempts / (ms / 1e3), "schedule": sched,
+           "rechecks": int(sum(o["rechecks"] for o in obs)),
+           "attempts_total": int(sum(o["attempts"] for o in obs))}
+    spins_out = [sco.spins(c) for c in range(len(params))]
+    sco.close()
+    progress(f"{name}: {ms:.3f} ms/step, {out['attempts_per_s']:.4g} attempts/s, schedule {sched}")
+    return out, spins_out
 
 
 def main() -> int:
@@ -63,6 +125,8 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nsw100", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the batched and mixed-precision legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the SCO step "
@@ -80,7 +144,8 @@ def main() -> int:
     N = p["L"] * p["L"]
     progress(f"init L={p['L']} T={p['T']} kappa={p['kappa']} n_sw={p['n_sw']}")
     sco = SCO([ChainParams(**p)], device="cuda:0")
-    stream = sco.stream
+    sched = sco.autotune(3)
+    progress(f"autotuned schedule: {sched}")
 
     for t in range(args.warmup):
         sco.step(t)
@@ -88,16 +153,8 @@ def main() -> int:
     progress(f"warmup {args.warmup} steps done")
 
     first = args.warmup
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    sco.run(first, args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    ms_per_step = ms / args.steps
-    value = N * p["n_sw"] * args.steps / (ms / 1e3)
+    ms_per_step = time_steps(sco, first, args.steps, torch)
+    value = N * p["n_sw"] / (ms_per_step / 1e3)
     obs = sco.observables()[0]
     progress(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} attempts/s")
 
@@ -107,7 +164,6 @@ def main() -> int:
     marks = sco.trace_read()
     sco.trace(False)
     trace = [(i, round(t, 2)) for i, t in marks]
-    progress("trace (id, us): " + " ".join(f"{i}:{t:.1f}" for i, t in trace))
 
     # per-phase times: the three phases as separate launches (k_step<1>, <2>, <4>)
     t0 = first + args.steps + 1
@@ -119,36 +175,46 @@ def main() -> int:
         sco.sweep(t0 + s, p["n_sw"])
         acc += np.array(sco.phase_times())
         o = sco.observables()[0]
-        stats.append((o["n_edges"], o["q"], o["kw_levels"], o["kw_rounds"]))
+        stats.append((o["n_edges"], o["q"], o["kw_levels"], o["kw_rounds"], o["accepted"], o["attempts"]))
     phase_ms = acc / args.phase_steps
     E = float(np.mean([s[0] for s in stats]))
     q = float(np.mean([s[1] for s in stats]))
     M = float(np.mean([s[2] for s in stats]))
+    accept = (stats[-1][4] - stats[0][4]) / max(1, stats[-1][5] - stats[0][5])
     tables = sco.tables(0)
     c = expected_candidates(tables["J"], p["T"], p["kappa"])
     k_mean = 2.0 * E / N
-    pb = phase_bytes(N, E, c, q, M, k_mean, p["kappa"] == 1.0, p["n_sw"])
+    tile = sched["tile_limit"]
+    P = int(np.floor(np.log2(tile / q))) if q > 0 else 0
+    pb = phase_bytes(N, E, c, M, P, k_mean, p["kappa"] == 1.0, p["n_sw"], accept)
     names = ["switch", "color", "sweep"]
-    dom = int(np.argmax(phase_ms))
-    dom_name = names[dom]
-    achieved = pb[dom_name] / (phase_ms[dom] / 1e3) / 1e9
+    step_bytes = sum(pb.values())
+    achieved = step_bytes / (ms_per_step / 1e3) / 1e9
     progress("phase ms: " + ", ".join(f"{n}={t:.3f}" for n, t in zip(names, phase_ms)))
 
     extra = {}
     if not args.no_nsw100 and p["n_sw"] == 1:
         sco100 = SCO([ChainParams(**{**p, "n_sw": 100})], device="cuda:0")
+        sco100.set_schedule(*[sched["blocks"], sched["tile_limit"]])
         sco100.run(0, 1)
-        torch.cuda.synchronize()
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record(sco100.stream)
-        sco100.run(1, 3)
-        f1.record(sco100.stream)
-        torch.cuda.synchronize()
-        ms100 = f0.elapsed_time(f1) / 3
+        ms100 = time_steps(sco100, 1, 3, torch)
         extra["n_sw_100"] = {"ms_per_step": ms100, "value": N * 100 / (ms100 / 1e3)}
         progress(f"n_sw=100: {ms100:.3f} ms/step")
         sco100.close()
+    if not args.no_workloads:
+        legs = {}
+        bp = workloads.batched()
+        legs["batched_64"], _ = workload_leg("batched 64 chains", bp, 10, torch, SCO, ChainParams)
+        for kappa in (1.0, 2.0):
+            mp0 = workloads.mixed_precision(precision=0, kappa=kappa)
+            mp1 = workloads.mixed_precision(precision=1, kappa=kappa)
+            r0, s0 = workload_leg(f"8xL2304+L4096 fp64 kappa={kappa}", mp0, 5, torch, SCO, ChainParams)
+            r1, s1 = workload_leg(f"8xL2304+L4096 fp32+recheck kappa={kappa}", mp1, 5, torch, SCO, ChainParams)
+            same = all(np.array_equal(x, y) for x, y in zip(s0, s1))
+            legs[f"mixed_9_chains_kappa{kappa:g}"] = {"fp64": r0, "fp32_recheck": r1,
+                                                     "identical_spins": bool(same),
+                                                     "speedup": r0["ms_per_step"] / r1["ms_per_step"]}
+        extra["workloads"] = legs
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,12 +256,12 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": {"switch": "k_step<1u>", "color": "k_step<2u>", "sweep": "k_step<4u>"}[dom_name],
-            "phase": dom_name,
-            "algorithmic_bytes_per_launch": pb[dom_name],
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+            "kernel": "k_step<7u>", "algorithmic_bytes_per_launch": step_bytes,
+            "phase_bytes": pb,
         },
         "cpu_baseline": cpu,
+        "schedule": sched,
         "phase_ms": dict(zip(names, [float(x) for x in phase_ms])),
         "phase_gbs": {n: pb[n] / (t / 1e3) / 1e9 for n, t in zip(names, phase_ms)},
         "graph": {"bonds_mean": E, "k_mean": k_mean, "q_mean": q, "kw_levels": M,

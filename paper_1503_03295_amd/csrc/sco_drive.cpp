@@ -55,6 +55,19 @@ int main(int argc, char** argv) {
               p.n_sw, bytes / 1e6);
   std::fflush(stdout);
 
+  // a plain device copy of known size, for scaling memory counters read around it
+  {
+    const size_t cb = static_cast<size_t>(256) << 20;
+    void *src = nullptr, *dst = nullptr;
+    HIP_OK(hipMalloc(&src, cb));
+    HIP_OK(hipMalloc(&dst, cb));
+    HIP_OK(hipMemsetAsync(src, 1, cb, s));
+    HIP_OK(hipMemcpyAsync(dst, src, cb, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipFree(src));
+    HIP_OK(hipFree(dst));
+    std::printf("calibration copy: %zu bytes read and written\n", cb);
+  }
   if ((rc = sco_run(ctx, 0, warmup))) return die("sco_run", rc);
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
