@@ -63,17 +63,29 @@ def phase_bytes(N, E, c, M, P, k_mean, hard, n_sw, accept):
     return {"switch": switch + assembly, "color": colour, "sweep": sweep}
 
 
+def kernel_source_hash():
+    """sha256 of the kernel sources with comments and blank lines removed (edits to
+    comments do not change the kernel)."""
+    import hashlib
+    import re
+
+    csrc = os.path.join(ROOT, "paper_1503_03295_amd", "csrc")
+    text = ""
+    for name in ("sco_kernels.hip", "sco_internal.h"):
+        src = open(os.path.join(csrc, name)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        lines = (re.sub(r"//.*$", "", line).strip() for line in src.splitlines())
+        text += "\n".join(line for line in lines if line) + "\n"
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per k_step<7u> launch from the committed rocprofv3 --pmc summary, or
     None when the kernel sources have changed since the counters were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "k_step_L2304_traffic.md")
-    csrc = os.path.join(ROOT, "paper_1503_03295_amd", "csrc")
     try:
         text = open(path).read()
-        h = hashlib.sha256(open(os.path.join(csrc, "sco_kernels.hip"), "rb").read() +
-                           open(os.path.join(csrc, "sco_internal.h"), "rb").read()).hexdigest()
+        h = kernel_source_hash()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()

@@ -157,6 +157,13 @@ __device__ __forceinline__ bool grid_barrier(SyncWords* s) {
 // until its own stores have completed, then the same arrival and bounded wait as
 // grid_barrier, without the L2 write-back and invalidation of the agent-scope fences,
 // so data that no class writes stays cached.  Returns false once a wait has timed out.
+//
+// Rule for its use (measured on gfx950): an XCD's own coherent store leaves the line
+// valid in that XCD's L2, and its later coherent loads are served from there.  So
+// between two full barriers every coherently written word must be written by blocks of
+// one XCD only (here: by the one block that owns the site for the whole phase), or a
+// former writer reads its own stale copy.  The KW levels rebalance sites between
+// levels, so each level ends with a full barrier; so does the tile phase.
 __device__ __forceinline__ bool class_barrier(SyncWords* s) {
   __shared__ uint32_t s_ok;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
