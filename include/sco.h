@@ -155,14 +155,14 @@ int sco_trace_read(sco_ctx* ctx, int32_t* ids, double* us, int max, int* n);
  * cooperative launch and the largest KW tile (sites) whose levels run in LDS.
  * Neither changes any result: every chain is a function of its parameters, spins and
  * step indices only.  sco_set_schedule: 0 selects the default (all co-resident
- * blocks, 16384-site tiles); blocks must be 1 .. that limit and tile_limit 64 .. 16384,
+ * blocks, 28672-site tiles); blocks must be 1 .. that limit and tile_limit 64 .. 28672,
  * else SCO_EINVAL. */
 int sco_set_schedule(sco_ctx* ctx, int blocks, int tile_limit);
 int sco_get_schedule(sco_ctx* ctx, int* blocks, int* tile_limit);
 
 /* Autotuner: times trial_steps (1 .. 1000) full steps for each candidate schedule
- * (grid sizes of 1, 3/4 and 1/2 of the co-resident limit x tile limits 16384, 8192,
- * 4096), starting every trial from the chain's current spins, and keeps the fastest.
+ * (grid sizes of 1, 3/4 and 1/2 of the co-resident limit x tile limits 28672, 14336,
+ * 7168), starting every trial from the chain's current spins, and keeps the fastest.
  * Afterwards the spins and counters are those from before the call; the bond graph
  * is not, so the next call that needs one must be sco_switch, sco_step or sco_run.
  * The chosen schedule and its time per step are returned through the non-NULL

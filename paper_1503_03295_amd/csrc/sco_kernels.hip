@@ -825,16 +825,19 @@ __device__ __forceinline__ int64_t pending_count(int N, int64_t h) {
 constexpr int kBatch = 2;
 constexpr int kScan = 4;
 
-// In-tile bond partners held in LDS; a site whose list would end beyond this many
-// entries reads its row from global memory instead.
-constexpr int kAdjCap = 16384;
+// In-tile bond lists held in LDS: for at most kBondedCap sites with in-tile bonds and
+// kAdjCap entries; a site beyond either reads its row from global memory instead.
+constexpr int kBondedCap = 8192;
+constexpr int kAdjCap = 10240;
 
 // LDS of the colouring and sweep phases: the tile arrays of the local levels, or the
 // bucket list of a block (block-local offsets) in the global levels and the sweeps.
 struct TileLds {
-  uint16_t cr[SCO_TILE_MAX];        // current colour | round of the decision << 8 (0: undecided)
-  uint16_t list[SCO_TILE_MAX / 2];  // pending sites bucketed by colour
-  uint16_t aoff[SCO_TILE_MAX + 1];  // in-tile bond list of site i: [aoff[i], aoff[i+1])
+  uint16_t cr[SCO_TILE_MAX];          // current colour | round of the decision << 8 (0: undecided)
+  uint16_t list[SCO_TILE_MAX / 2];    // pending sites bucketed by colour
+  uint32_t bmask[SCO_TILE_MAX / 32];  // bit i: site i has in-tile bonds
+  uint16_t brank[SCO_TILE_MAX / 32];  // sites with in-tile bonds before word w
+  uint16_t boff[kBondedCap + 1];      // the r-th such site's partners: adj[boff[r], boff[r+1])
   uint16_t adj[kAdjCap];
 };
 constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
@@ -849,14 +852,21 @@ union PhaseLds {
 __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared& ks, TileLds& tl) {
   uint16_t* const t_cr = tl.cr;
   uint16_t* const t_list = tl.list;
-  uint16_t* const t_aoff = tl.aoff;
+  uint32_t* const t_bmask = tl.bmask;
+  uint16_t* const t_brank = tl.brank;
+  uint16_t* const t_boff = tl.boff;
   uint16_t* const t_adj = tl.adj;
   __shared__ int32_t t_off[SCO_MAXQ + 1];
   __shared__ int32_t t_fill[SCO_MAXQ];
   __shared__ int32_t t_wsum[kWaves];
-  __shared__ int32_t t_rounds;
+  __shared__ int32_t t_rounds, t_nbonded;
   const uint32_t lane = lane_id();
   const int wave = threadIdx.x >> 6;
+  const int tid = static_cast<int>(threadIdx.x);
+  // rank of a site with in-tile bonds among those of the tile
+  auto bond_rank = [&](int i) {
+    return static_cast<int>(t_brank[i >> 5]) + __popc(t_bmask[i >> 5] & ((1u << (i & 31)) - 1u));
+  };
   for (int tile = blockIdx.x; tile < ks.ntiles; tile += gridDim.x) {
     int c = 0;
     while (c + 1 < a.n_chains && ks.kc[c + 1].tile0 <= tile) ++c;
@@ -870,26 +880,58 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     // half-group sizes are exact multiply-highs
     const uint32_t mq = magic16(static_cast<uint32_t>(q)), mL = magic16(static_cast<uint32_t>(L));
     const int y0 = fdiv(v0, K.inv_L), x0 = v0 - y0 * L;
-    for (int i = threadIdx.x; i < n; i += kBlock) t_cr[i] = static_cast<uint16_t>(i - div16(i, mq) * q);
+    const int nw = (n + 31) >> 5;
     if (P > 0) {
-      // in-tile partner counts, then offsets (block scan), then the partners in row order
-      for (int i = threadIdx.x; i < n; i += kBlock) {
-        int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
-        row_checked(a, r0, r1);
+      // 1. in-tile partner counts (held in cr until the colours start) and the mask of
+      //    sites that have any, one ballot per 64 consecutive sites
+      for (int ib = 0; ib < n; ib += kBlock) {
+        const int i = ib + tid;
         int k = 0;
-        for (int e = r0; e < r1; ++e) {
-          const int j = a.col[e] - gt0;
-          k += (j >= 0 && j < n) ? 1 : 0;
+        if (i < n) {
+          int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+          row_checked(a, r0, r1);
+          for (int e = r0; e < r1; ++e) {
+            const int j = a.col[e] - gt0;
+            k += (j >= 0 && j < n) ? 1 : 0;
+          }
+          t_cr[i] = static_cast<uint16_t>(k);
         }
-        t_aoff[i + 1] = static_cast<uint16_t>(k);
+        const uint64_t m = __ballot(k > 0);
+        const int w0 = (ib + wave * 64) >> 5;
+        if (lane == 0 && w0 < nw) t_bmask[w0] = static_cast<uint32_t>(m);
+        if (lane == 0 && w0 + 1 < nw) t_bmask[w0 + 1] = static_cast<uint32_t>(m >> 32);
       }
       __syncthreads();
+      // 2. ranks: exclusive prefix of the word popcounts (nw <= 1024 words)
       {
-        constexpr int kPer = SCO_TILE_MAX / kBlock;
-        const int b0 = 1 + static_cast<int>(threadIdx.x) * kPer;
+        const int cnt = tid < nw ? __popc(t_bmask[tid]) : 0;
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int x = __shfl_up(incl, o);
+          if (lane >= static_cast<uint32_t>(o)) incl += x;
+        }
+        if (lane == 63) t_wsum[wave] = incl;
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wave; ++w) off += t_wsum[w];
+        if (tid < nw) t_brank[tid] = static_cast<uint16_t>(off + incl - cnt);
+        if (tid == kBlock - 1) t_nbonded = off + incl;
+      }
+      __syncthreads();
+      // 3. list offsets of the first kBondedCap such sites (block scan, saturating)
+      const int nb = min(t_nbonded, kBondedCap);
+      for (int i = tid; i < n; i += kBlock)
+        if ((t_bmask[i >> 5] >> (i & 31)) & 1u) {
+          const int r = bond_rank(i);
+          if (r < kBondedCap) t_boff[r + 1] = t_cr[i];
+        }
+      __syncthreads();
+      {
+        constexpr int kPer = (kBondedCap + kBlock - 1) / kBlock;
+        const int b0 = 1 + tid * kPer;
         int s = 0;
         for (int k = 0; k < kPer; ++k)
-          if (b0 + k <= n) s += t_aoff[b0 + k];
+          if (b0 + k <= nb) s += t_boff[b0 + k];
         int incl = s;
         for (int o = 1; o < 64; o <<= 1) {
           const int x = __shfl_up(incl, o);
@@ -900,17 +942,21 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         int run = incl - s;
         for (int w = 0; w < wave; ++w) run += t_wsum[w];
         for (int k = 0; k < kPer; ++k)
-          if (b0 + k <= n) {
-            run += t_aoff[b0 + k];
-            t_aoff[b0 + k] = static_cast<uint16_t>(min(run, 65535));
+          if (b0 + k <= nb) {
+            run += t_boff[b0 + k];
+            t_boff[b0 + k] = static_cast<uint16_t>(min(run, 65535));
           }
-        if (threadIdx.x == 0) t_aoff[0] = 0;
+        if (tid == 0) t_boff[0] = 0;
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < n; i += kBlock) {
-        const int e_end = t_aoff[i + 1];
+      // 4. the partners, in row order
+      for (int i = tid; i < n; i += kBlock) {
+        if (!((t_bmask[i >> 5] >> (i & 31)) & 1u)) continue;
+        const int r = bond_rank(i);
+        if (r >= kBondedCap) continue;
+        const int e_end = t_boff[r + 1];
         if (e_end > kAdjCap) continue;  // read from global memory when needed
-        int w = t_aoff[i];
+        int w = t_boff[r];
         int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
         row_checked(a, r0, r1);
         for (int e = r0; e < r1 && w < e_end; ++e) {
@@ -920,6 +966,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       }
       __syncthreads();
     }
+    // level 0: colour i mod q (cr held the partner counts until here)
+    for (int i = tid; i < n; i += kBlock) t_cr[i] = static_cast<uint16_t>(i - div16(i, mq) * q);
+    __syncthreads();
     if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 30);
     for (int p = 1; p <= P; ++p) {
       // pending sites: k -> (2 (k / H) + 1) H + k mod H, H = q 2^(p-1) the half-group
@@ -993,13 +1042,17 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
           nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
 #pragma unroll
           for (int u = 0; u < 4; ++u) visit(nb[u] >= 0 ? nb[u] - v0 : -1);
-          const int e0 = t_aoff[i], e1 = t_aoff[i + 1];
-          if (e1 <= kAdjCap) {
-            for (int e = e0; e < e1; ++e) visit(t_adj[e]);
-          } else {
-            int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
-            row_checked(a, r0, r1);
-            for (int e = r0; e < r1; ++e) visit(a.col[e] - gt0);
+          const uint32_t mw = t_bmask[i >> 5];
+          if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
+            const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
+            const int e1 = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
+            if (e1 <= kAdjCap) {
+              for (int e = t_boff[r]; e < e1; ++e) visit(t_adj[e]);
+            } else {
+              int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
+              row_checked(a, r0, r1);
+              for (int e = r0; e < r1; ++e) visit(a.col[e] - gt0);
+            }
           }
           int nc = taken.first_free();
           if (nc >= q) {
