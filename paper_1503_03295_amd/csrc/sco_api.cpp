@@ -50,7 +50,7 @@ struct Layout {
   std::vector<int64_t> vbase;
   std::vector<size_t> off_theta, off_delta, off_delta32;
   size_t off_sync = 0, off_cd = 0, off_st = 0, off_chunk = 0, off_srcbase = 0;
-  size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0;
+  size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0, off_er = 0;
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_ts = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
@@ -118,6 +118,7 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_ea = take(sizeof(int32_t) * lay.cap_und);
   lay.off_eb = take(sizeof(int32_t) * lay.cap_und);
   lay.off_em = take(sizeof(int32_t) * lay.cap_und);
+  lay.off_er = take(sizeof(int32_t) * lay.cap_und);
   lay.off_col = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
   lay.off_attr = take(sizeof(int32_t) * 2 * static_cast<size_t>(lay.cap_und));
   lay.off_color = take(sizeof(uint16_t) * G);
@@ -484,6 +485,7 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   a.ea = at<int32_t>(c, L.off_ea);
   a.eb = at<int32_t>(c, L.off_eb);
   a.em = at<int32_t>(c, L.off_em);
+  a.er = at<int32_t>(c, L.off_er);
   a.col = at<int32_t>(c, L.off_col);
   a.attr = at<int32_t>(c, L.off_attr);
   a.color = at<uint16_t>(c, L.off_color);

@@ -72,8 +72,9 @@ struct StepArgs {
   int8_t* spin;
   int32_t* deg;           // [G] degrees (cleared by the switching phase)
   int32_t* row_ptr;       // [G + 1]
-  int32_t* fill;          // [G] scatter cursors (cleared by the switching phase)
+  int32_t* fill;          // [G] scatter cursors: cleared, then set to each owner's survivor count
   int32_t *ea, *eb, *em;  // survivors: owner, partner (global sites), displacement index
+  int32_t* er;            // survivor's rank among its owner's survivors
   int32_t* col;           // [2 * cap] neighbour (global site)
   int32_t* attr;          // [2 * cap] displacement index
   uint16_t* color;        // [G]

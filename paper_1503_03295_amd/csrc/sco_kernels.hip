@@ -27,6 +27,10 @@ namespace {
 
 constexpr int kBlock = SCO_CHUNK;  // a block of per-site threads is one chunk
 constexpr int kWaves = kBlock / 64;
+// Items per thread whose loads are issued together: in colour classes (kBatch) and in
+// scans over sites or survivors (kScan).
+constexpr int kBatch = 3;
+constexpr int kScan = 4;
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of multiply/xor with the Weyl key
@@ -269,8 +273,9 @@ __device__ __forceinline__ int wave_max(int v) {
 // atomicMax of per-lane values into a per-chain LDS array; one atomic per wave when
 // the lanes with a value share the chain (all lanes must call; c < 0: no value)
 __device__ __forceinline__ void wave_max_to(int* per_chain, int c, int val) {
-  const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(__ballot(c >= 0))) - 1);
-  if (__ballot(c >= 0) == 0) return;
+  const uint64_t has = __ballot(c >= 0);
+  if (has == 0) return;
+  const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(has)) - 1);
   if (__ballot(c >= 0 && c != c0) == 0) {
     const int m = wave_max(c >= 0 ? val : 0);
     if (lane_id() == 0) atomicMax(&per_chain[c0], m);
@@ -286,6 +291,21 @@ __device__ __forceinline__ void row_checked(const StepArgs& a, int& r0, int& r1)
   if (r0 < 0 || r1 < r0 || r1 > cap2) {
     set_flag(a.sync, SCO_FLAG_STATE);
     r0 = r1 = 0;
+  }
+}
+
+// atomicAdd of per-lane values into a per-chain LDS array; one atomic per wave when
+// the lanes with a value share the chain (all lanes must call; c < 0: no value)
+__device__ __forceinline__ void wave_sum_to(int* per_chain, int c, int val) {
+  const uint64_t has = __ballot(c >= 0);
+  if (has == 0) return;
+  const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(has)) - 1);
+  if (__ballot(c >= 0 && c != c0) == 0) {
+    int t = c >= 0 ? val : 0;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane_id() == 0 && t != 0) atomicAdd(&per_chain[c0], t);
+  } else if (c >= 0 && val != 0) {
+    atomicAdd(&per_chain[c], val);
   }
 }
 
@@ -392,17 +412,20 @@ struct Owner {
   double Cpos;     // C at pos
   uint32_t slo, shi;  // second half of the last Philox output: the next (odd) draw
   int si;          // the owner's spin
+  int ns;          // survivors of the owner stored so far
   bool live;
 };
 
 // Starts the next owner site of this thread in chunks [next, ch1); false when none
 // is left.
-__device__ __forceinline__ bool owner_take(const StepArgs& a, Owner& o, int& next, int ch1) {
+// desc_of(c) gives chain c's descriptor (with a block-uniform chain, from scalar loads).
+template <class Desc>
+__device__ __forceinline__ bool owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, int& next, int ch1) {
   while (next < ch1) {
     const int64_t g = (static_cast<int64_t>(next) << SCO_CHUNK_SHIFT) + threadIdx.x;
     const int c = a.chunk_chain[next];
     ++next;
-    const ChainDesc& d = a.cd[c];
+    const ChainDesc& d = desc_of(c);
     const int v = static_cast<int>(g - d.vbase);
     if (v >= d.N) continue;  // chunk padding
     o.g = g;
@@ -414,6 +437,7 @@ __device__ __forceinline__ bool owner_take(const StepArgs& a, Owner& o, int& nex
     o.k = 0;
     o.Cpos = 0.0;
     o.si = a.spin[g];
+    o.ns = 0;
     o.live = true;
     return true;
   }
@@ -444,8 +468,10 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, double target, i
 // 1 the exponential gap is computed in FP32; the FP64 outcome is certain unless the
 // target lies within `tol` of C_top or of the table values it was compared with, and
 // then the gap is recomputed in FP64 (counted in `rechecks`).
-__device__ __forceinline__ bool owner_draw(const StepArgs& a, uint32_t step, Owner& o, int& j, int& m) {
-  const ChainDesc& d = a.cd[o.c];
+template <class Desc>
+__device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_of, uint32_t step, Owner& o, int& j,
+                                           int& m) {
+  const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
     o.live = false;
@@ -529,9 +555,10 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
   if (threadIdx.x == 0) s_count = 0;
   __syncthreads();
   const uint32_t lane = lane_id();
-  auto append = [&](bool f, int64_t g, int c, int j, int m) {
+  // returns the owner's count of stored survivors after this append
+  auto append = [&](bool f, int64_t g, int c, int j, int m, int ns) -> int {
     const uint64_t mask = __ballot(f);
-    if (mask == 0) return;
+    if (mask == 0) return ns;
     const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
     uint32_t e0 = 0;
     if (static_cast<int>(lane) == leader) e0 = atomicAdd(&s_count, static_cast<uint32_t>(__popcll(mask)));
@@ -544,25 +571,50 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
         a.ea[e] = static_cast<int32_t>(g);
         a.eb[e] = gj;
         a.em[e] = m;
+        a.er[e] = ns++;
         atomicAdd(&a.deg[g], 1);
         atomicAdd(&a.deg[gj], 1);
       } else {
         set_flag(a.sync, SCO_FLAG_OVERFLOW);
       }
     }
+    return ns;
   };
-  int next = ch0;
-  Owner A, B;
-  owner_take(a, A, next, ch1);
-  owner_take(a, B, next, ch1);
-  while (__ballot(A.live || B.live) != 0) {
-    int jA = -1, mA = 0, jB = -1, mB = 0;
-    const bool fA = A.live && owner_draw(a, step, A, jA, mA);
-    const bool fB = B.live && owner_draw(a, step, B, jB, mB);
-    append(fA, A.g, A.c, jA, mA);
-    append(fB, B.g, B.c, jB, mB);
-    if (!A.live) owner_take(a, A, next, ch1);
-    if (!B.live) owner_take(a, B, next, ch1);
+  auto run = [&](const auto& desc_of) {
+    int next = ch0;
+    Owner A, B;
+    A.ns = B.ns = 0;
+    owner_take(a, desc_of, A, next, ch1);
+    owner_take(a, desc_of, B, next, ch1);
+    while (__ballot(A.live || B.live) != 0) {
+      int jA = -1, mA = 0, jB = -1, mB = 0;
+      const bool fA = A.live && owner_draw(a, desc_of, step, A, jA, mA);
+      const bool fB = B.live && owner_draw(a, desc_of, step, B, jB, mB);
+      A.ns = append(fA, A.g, A.c, jA, mA, A.ns);
+      B.ns = append(fB, B.g, B.c, jB, mB, B.ns);
+      // an ended owner's survivor count starts its row's cursor for the partners
+      if (!A.live) {
+        if (A.ns) a.fill[A.g] = A.ns;
+        A.ns = 0;
+        owner_take(a, desc_of, A, next, ch1);
+      }
+      if (!B.live) {
+        if (B.ns) a.fill[B.g] = B.ns;
+        B.ns = 0;
+        owner_take(a, desc_of, B, next, ch1);
+      }
+    }
+  };
+  if (ch0 < ch1) {
+    // the chunks of a block usually belong to one chain: its descriptor is then
+    // block-uniform and read with scalar loads
+    const int c_lo = a.chunk_chain[ch0], c_hi = a.chunk_chain[ch1 - 1];
+    if (c_lo == c_hi) {
+      const ChainDesc& d0 = a.cd[c_lo];
+      run([&](int) -> const ChainDesc& { return d0; });
+    } else {
+      run([&](int c) -> const ChainDesc& { return a.cd[c]; });
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0)
@@ -571,90 +623,80 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
 }
 
 // ------------------------------------------------------------------ prefix sum
-// Single-pass exclusive scan (decoupled look-back) of n int32 values: tile t
-// publishes its aggregate, then its inclusive prefix, in one 64-bit word
-// (epoch:24 | state:8 | value:32) so that one relaxed atomic carries both.  Tiles are
-// taken in increasing order by every block, so the tile a block waits on is owned by
-// a block that is not waiting on it.  out[n] = total.  out may alias in.
+// Exclusive scan of n int32 values in tiles of kTile: (1) every block sums its tiles
+// into agg[t]; (2) a device-wide barrier; (3) each block adds the sums of the tiles
+// before each of its tiles and scans the tile.  Global memory is read and written in
+// coalesced rows (item k * kBlock + thread); the scan order goes through LDS, padded
+// one word in 32 against bank conflicts.  out[n] = total.  out may alias in.
 constexpr int kItems = 16;
 constexpr int kTile = kBlock * kItems;
+constexpr int kScanLds = kTile + kTile / 32;  // words of the padded tile in LDS
 
-__device__ __forceinline__ bool scan_lookback(const int32_t* in, int64_t n, int32_t* out, unsigned long long* ts,
-                              uint32_t epoch, SyncWords* sync) {
+__device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, int32_t* out, long long* agg,
+                                              int32_t* lds, SyncWords* sync) {
   __shared__ int32_t wsum[kWaves];
-  __shared__ int32_t s_excl;
-  const int64_t nt = (n + kTile - 1) / kTile;
-  const unsigned long long tag = static_cast<unsigned long long>(epoch & 0xFFFFFFu) << 40;
-  bool ok = true;
-  for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const int64_t base = t * kTile + static_cast<int64_t>(threadIdx.x) * kItems;
-    int32_t vals[kItems];
+  const int n = static_cast<int>(n64);  // G < 2^31
+  const int nt = (n + kTile - 1) / kTile;
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const int tid = static_cast<int>(threadIdx.x);
+  // padded LDS addresses (one word in 32): row item k of this thread at
+  // rowb + k kRow, scan item i at colb + i
+  const int rowb = tid + (tid >> 5), colb = tid * kItems + (tid >> 1);
+  constexpr int kRow = kBlock + kBlock / 32;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int tb = t * kTile + tid;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int idx = tb + k * kBlock;
+      s += idx < n ? in[idx] : 0;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) agg[t] = s;
+  }
+  if (!grid_barrier(sync)) return false;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int tb = t * kTile + tid;
+    // coalesced rows into LDS
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int idx = tb + k * kBlock;
+      lds[rowb + k * kRow] = idx < n ? in[idx] : 0;
+    }
+    // sum of the tiles before t
+    long long pre = 0;
+    for (int k = tid; k < t; k += kBlock) pre += agg[k];
+    pre = block_sum(pre);  // in every thread; its barriers also order the LDS stores
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const int64_t idx = base + i;
-      vals[i] = idx < n ? in[idx] : 0;
-      s += vals[i];
-    }
+    for (int i = 0; i < kItems; ++i) s += lds[colb + i];
     int32_t incl = s;
-    const uint32_t lane = lane_id();
     for (int o = 1; o < 64; o <<= 1) {
       const int32_t x = __shfl_up(incl, o);
       if (lane >= static_cast<uint32_t>(o)) incl += x;
     }
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
-    int32_t woff = 0, agg = 0;
-    for (int i = 0; i < kWaves; ++i) {
-      woff += i < w ? wsum[i] : 0;
-      agg += wsum[i];
-    }
-    if (threadIdx.x == 0) {
-      int32_t excl = 0;
-      if (t == 0) {
-        st_relaxed(&ts[t], tag | (2ull << 32) | static_cast<uint32_t>(agg));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      } else {
-        st_relaxed(&ts[t], tag | (1ull << 32) | static_cast<uint32_t>(agg));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        int64_t jdx = t - 1;
-        uint32_t spins = 0;
-        while (jdx >= 0) {
-          const unsigned long long wv = spins ? ld_poll(&ts[jdx]) : ld_relaxed(&ts[jdx]);
-          uint32_t state = static_cast<uint32_t>((wv >> 32) & 0xFFu);
-          if ((wv >> 40) != (tag >> 40) || state > 2u) state = 0;  // another launch's word
-          if (state == 0) {
-            if (timed_out(sync) || ++spins > kSpinLimit) {
-              set_flag(sync, SCO_FLAG_TIMEOUT);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += static_cast<int32_t>(wv & 0xFFFFFFFFu);
-          if (state == 2) break;
-          --jdx;
-        }
-        st_relaxed(&ts[t], tag | (2ull << 32) | static_cast<uint32_t>(excl + agg));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      }
-      s_excl = excl;
-    }
-    __syncthreads();
-    if (timed_out(sync)) ok = false;
-    int32_t run = s_excl + woff + incl - s;
+    int32_t woff = 0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    int32_t run = static_cast<int32_t>(pre) + woff + incl - s;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-      const int64_t idx = base + i;
-      if (idx < n) out[idx] = run;
-      run += vals[i];
+      const int32_t v = lds[colb + i];
+      lds[colb + i] = run;
+      run += v;
     }
     if (t == nt - 1 && threadIdx.x == kBlock - 1) out[n] = run;
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int idx = tb + k * kBlock;
+      if (idx < n) out[idx] = lds[rowb + k * kRow];
+    }
+    __syncthreads();
   }
-  return ok;
+  return true;
 }
 
 // both directions of every survivor into the CSR
@@ -662,71 +704,129 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
+  const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
   for (int ch = ch0; ch < ch1; ++ch) {
     const uint32_t e0 = static_cast<uint32_t>(ch) * cap_chunk, e1 = e0 + a.ecount[ch];
-    const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      const int32_t u = a.ea[e], w = a.eb[e], m = a.em[e];
-      const int64_t pu = a.row_ptr[u] + atomicAdd(&a.fill[u], 1);
-      const int64_t pw = a.row_ptr[w] + atomicAdd(&a.fill[w], 1);
-      if (pu < 0 || pu >= cap2 || pw < 0 || pw >= cap2) {  // cannot happen: degrees sum to 2 e
-        set_flag(a.sync, SCO_FLAG_OVERFLOW);
-        continue;
+    // kScan survivors per thread and iteration, their loads and cursor atomics
+    // issued together
+    for (uint32_t eb = e0; eb < e1; eb += kScan * kBlock) {
+      int32_t u[kScan], w[kScan], m[kScan], rk[kScan];
+      bool ok[kScan];
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        const uint32_t e = eb + r * kBlock + threadIdx.x;
+        ok[r] = e < e1;
+        u[r] = w[r] = m[r] = rk[r] = 0;
+        if (ok[r]) {
+          u[r] = a.ea[e];
+          w[r] = a.eb[e];
+          m[r] = a.em[e];
+          rk[r] = a.er[e];
+        }
       }
-      a.col[pu] = w;
-      a.attr[pu] = m;
-      a.col[pw] = u;
-      a.attr[pw] = m;
+      // the owner's entries first, at their rank; the partners' after them, through
+      // the cursor that starts at the owner's survivor count
+      int64_t pu[kScan], pw[kScan];
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        pu[r] = pw[r] = -1;
+        if (ok[r]) {
+          pu[r] = static_cast<int64_t>(a.row_ptr[u[r]]) + rk[r];
+          pw[r] = a.row_ptr[w[r]] + atomicAdd(&a.fill[w[r]], 1);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        if (!ok[r]) continue;
+        if (pu[r] < 0 || pu[r] >= cap2 || pw[r] < 0 || pw[r] >= cap2) {  // cannot happen: degrees sum to 2 e
+          set_flag(a.sync, SCO_FLAG_OVERFLOW);
+          continue;
+        }
+        a.col[pu[r]] = w[r];
+        a.attr[pu[r]] = m[r];
+        a.col[pw[r]] = u[r];
+        a.attr[pw[r]] = m[r];
+      }
     }
   }
 }
 
 // Sorts each row ascending by neighbour; union degree |CSR(v) u NN(v)|; Delta and
-// directed bond count per chain.
+// directed bond count per chain.  Block b takes a contiguous range of chunks, kScan
+// chunks per iteration with their row offsets loaded together; the per-chain maximum
+// and sum gather in LDS (one atomic per wave when the wave is one chain) and reach
+// the chain states once per block.
 __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < a.G; base += stride) {
-    const int c = a.chunk_chain[base >> SCO_CHUNK_SHIFT];
-    const ChainDesc& d = a.cd[c];
-    const int64_t g = base + threadIdx.x;
-    const int v = static_cast<int>(g - d.vbase);
-    int udeg = 0, rowlen = 0;
-    if (v < d.N) {
-      int r0 = a.row_ptr[g], r1 = a.row_ptr[g + 1];
-      row_checked(a, r0, r1);
-      rowlen = r1 - r0;
-      int32_t* __restrict__ col = a.col;
-      int32_t* __restrict__ attr = a.attr;
-      for (int q = r0 + 1; q < r1; ++q) {
-        const int32_t kc = col[q], ka = attr[q];
-        int b = q - 1;
-        while (b >= r0 && col[b] > kc) {
-          col[b + 1] = col[b];
-          attr[b + 1] = attr[b];
-          --b;
-        }
-        col[b + 1] = kc;
-        attr[b + 1] = ka;
-      }
-      const int y = fdiv(v, d.inv_L), x = v - y * d.L;
-      int nb[4];
-      nn_sites(x, y, d.L, d.periodic, nb);
-      udeg = rowlen;
+  __shared__ int32_t rmax[SCO_MAXCHAINS];
+  __shared__ int32_t rsum[SCO_MAXCHAINS];
+  const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
+  const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
+  for (int c = threadIdx.x; c < a.n_chains; c += kBlock) rmax[c] = rsum[c] = 0;
+  __syncthreads();
+  for (int chb = ch0; chb < ch1; chb += kScan) {
+    int cs[kScan], r0[kScan], r1[kScan];
+    bool ok[kScan];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (nb[q] < 0) continue;
-        const int32_t gu = static_cast<int32_t>(d.vbase + nb[q]);
-        bool dup = false;
-        for (int b = r0; b < r1; ++b) dup |= (col[b] == gu);
-        udeg += dup ? 0 : 1;
+    for (int r = 0; r < kScan; ++r) {
+      const int ch = chb + r;
+      ok[r] = false;
+      cs[r] = -1;
+      r0[r] = r1[r] = 0;
+      if (ch < ch1) {
+        cs[r] = a.chunk_chain[ch];
+        const int64_t g = (static_cast<int64_t>(ch) << SCO_CHUNK_SHIFT) + threadIdx.x;
+        ok[r] = static_cast<int>(g - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
+        if (ok[r]) {
+          r0[r] = a.row_ptr[g];
+          r1[r] = a.row_ptr[g + 1];
+        }
       }
     }
-    const int mx = block_max(udeg);
-    const int tot = block_sum(rowlen);
-    if (threadIdx.x == 0) {
-      atomicMax(&a.st[c].delta_union, mx);
-      atomicAdd(&a.st[c].n_edges, static_cast<uint32_t>(tot));
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) {
+      int udeg = 0, rowlen = 0;
+      if (ok[r]) {
+        const ChainDesc& d = a.cd[cs[r]];
+        const int64_t g = (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x;
+        const int v = static_cast<int>(g - d.vbase);
+        int q0 = r0[r], q1 = r1[r];
+        row_checked(a, q0, q1);
+        rowlen = q1 - q0;
+        int32_t* __restrict__ col = a.col;
+        int32_t* __restrict__ attr = a.attr;
+        for (int q = q0 + 1; q < q1; ++q) {
+          const int32_t kc = col[q], ka = attr[q];
+          int b = q - 1;
+          while (b >= q0 && col[b] > kc) {
+            col[b + 1] = col[b];
+            attr[b + 1] = attr[b];
+            --b;
+          }
+          col[b + 1] = kc;
+          attr[b + 1] = ka;
+        }
+        const int y = fdiv(v, d.inv_L), x = v - y * d.L;
+        int nb[4];
+        nn_sites(x, y, d.L, d.periodic, nb);
+        udeg = rowlen;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (nb[t] < 0) continue;
+          const int32_t gu = static_cast<int32_t>(d.vbase + nb[t]);
+          bool dup = false;
+          for (int b = q0; b < q1; ++b) dup |= (col[b] == gu);
+          udeg += dup ? 0 : 1;
+        }
+      }
+      const int c = ok[r] ? cs[r] : -1;
+      wave_max_to(rmax, c, udeg);
+      wave_sum_to(rsum, c, rowlen);
     }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
+    if (rmax[c] > 0) atomicMax(&a.st[c].delta_union, rmax[c]);
+    if (rsum[c] > 0) atomicAdd(&a.st[c].n_edges, static_cast<uint32_t>(rsum[c]));
   }
 }
 
@@ -820,10 +920,6 @@ __device__ __forceinline__ int64_t pending_count(int N, int64_t h) {
   return full * h + (rem > h ? rem - h : 0);
 }
 
-// Sites per thread whose loads are issued together: in colour classes (kBatch) and
-// in bucketing scans (kScan).
-constexpr int kBatch = 2;
-constexpr int kScan = 4;
 
 // In-tile bond lists held in LDS: for at most kBondedCap sites with in-tile bonds and
 // kAdjCap entries; a site beyond either reads its row from global memory instead.
@@ -841,6 +937,7 @@ struct TileLds {
   uint16_t adj[kAdjCap];
 };
 constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
+static_assert(kListCap >= kScanLds, "the scan stages a padded tile in the phase LDS");
 union PhaseLds {
   TileLds tile;
   int32_t list[kListCap];
@@ -1543,7 +1640,8 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, uint
     mark(a.trace, 2);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
-    if (!scan_lookback(a.deg, a.G, a.row_ptr, a.scan_ts, epoch, a.sync)) return false;
+    if (!scan_two_pass(a.deg, a.G, a.row_ptr, reinterpret_cast<long long*>(a.scan_ts), lds.list, a.sync))
+      return false;
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 4);
     phase_scatter(a);
