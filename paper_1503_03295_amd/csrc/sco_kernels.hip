@@ -30,6 +30,7 @@ constexpr int kWaves = kBlock / 64;
 // Items per thread whose loads are issued together: in colour classes (kBatch) and in
 // scans over sites or survivors (kScan).
 constexpr int kBatch = 3;
+constexpr int kBatchKW = 4;  // in the KW classes
 constexpr int kScan = 4;
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -1278,15 +1279,15 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     for (int cc = qmax - 1; cc >= 0; --cc) {
       const int b0 = boff[cc], b1 = boff[cc + 1];
       // every thread of the block runs the same number of iterations; each takes
-      // kBatch sites of the class and loads everything they read before deciding any
+      // kBatchKW sites of the class and loads everything they read before deciding any
       // (sites of one class never read each other's words)
-      for (int kb = b0; kb < b1; kb += kBatch * kBlock) {
-        int gs[kBatch], cs[kBatch], rb[kBatch], re[kBatch];
-        int nbs[kBatch][4];
-        uint32_t wn[kBatch][4];
-        bool ok[kBatch];
+      for (int kb = b0; kb < b1; kb += kBatchKW * kBlock) {
+        int gs[kBatchKW], cs[kBatchKW], rb[kBatchKW], re[kBatchKW];
+        int nbs[kBatchKW][4];
+        uint32_t wn[kBatchKW][4];
+        bool ok[kBatchKW];
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
+        for (int r = 0; r < kBatchKW; ++r) {
           const int kx = kb + r * kBlock + tid;
           ok[r] = kx < b1;
           gs[r] = 0;
@@ -1313,24 +1314,22 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
             row_checked(a, rb[r], re[r]);
           }
         }
-        // the first two bond partners and their words
-        int pb[kBatch][2];
-        uint32_t wb[kBatch][2];
+        // the first bond partner and its word
+        int pb[kBatchKW];
+        uint32_t wb[kBatchKW];
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
+        for (int r = 0; r < kBatchKW; ++r) {
           const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-          pb[r][0] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
-          pb[r][1] = re[r] > rb[r] + 1 ? a.col[rb[r] + 1] - vb : -1;
+          pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
         }
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
+        for (int r = 0; r < kBatchKW; ++r) {
           const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-#pragma unroll
-          for (int t = 0; t < 2; ++t) wb[r][t] = pb[r][t] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r][t]]) : 0u;
+          wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
         }
-        int cdone[kBatch], rdone[kBatch];
+        int cdone[kBatchKW], rdone[kBatchKW];
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
+        for (int r = 0; r < kBatchKW; ++r) {
           cdone[r] = -1;
           rdone[r] = 0;
           if (!ok[r]) continue;
@@ -1356,10 +1355,8 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             if (nbs[r][t] >= 0) visit(nbs[r][t], wn[r][t]);
-#pragma unroll
-          for (int t = 0; t < 2; ++t)
-            if (pb[r][t] >= 0) visit(pb[r][t], wb[r][t]);
-          for (int e = rb[r] + 2; e < re[r]; ++e) {
+          if (pb[r] >= 0) visit(pb[r], wb[r]);
+          for (int e = rb[r] + 1; e < re[r]; ++e) {
             const int u = a.col[e] - vb;
             visit(u, ld_relaxed(&a.kw_word[vb + u]));
           }
@@ -1375,7 +1372,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
           rdone[r] = rmax + 1;
         }
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
+        for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
       }
       if (p == ks.pmin + 1) mark(a.trace, 300 + 2 * cc);
       // between the classes of a level only the words change (coherent accesses); the
