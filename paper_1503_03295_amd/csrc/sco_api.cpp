@@ -53,7 +53,7 @@ struct Layout {
   size_t off_spin = 0, off_deg = 0, off_row = 0, off_fill = 0, off_ea = 0, off_eb = 0, off_em = 0, off_er = 0;
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_spin_bak = 0, off_st_bak = 0;
-  size_t off_ts = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
+  size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -126,8 +126,8 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_rec = take(sizeof(int4) * G);
   lay.off_ecount = take(sizeof(uint32_t) * lay.nchunks);
   lay.off_trace = take(sizeof(unsigned long long) * SCO_TRACE_SLOTS);
-  lay.ntiles = G / (16 * SCO_CHUNK) + 2;
-  lay.off_ts = take(sizeof(unsigned long long) * lay.ntiles);
+  lay.ntiles = G / (16 * SCO_CHUNK) + 2;  // tiles of the degree scan
+  lay.off_agg = take(sizeof(long long) * lay.ntiles);
   lay.off_spin_bak = take(G);  // autotuning trials restore the chain from here
   lay.off_st_bak = take(sizeof(ChainState) * n);
   lay.off_obs = take(sizeof(unsigned long long) * 2 * n);
@@ -188,7 +188,6 @@ struct sco_ctx {
   int launched_blocks = 0;         // grid of the last launch (its barrier counters)
   int nsw_max = 0;
   int graph_state = 0;  // 0 no bond graph yet, 1 switched, 2 switched and coloured
-  uint32_t epoch = 0;
   bool trace_on = false;
   double wall_mhz = 100.0;
   unsigned long long* pinned = nullptr;            // read-back staging
@@ -238,16 +237,9 @@ int consume_flags(sco_ctx* c) {
   return SCO_EINTERNAL;
 }
 
-// Launches `phases` for SCO step `step`.  Each launch gets its own 24-bit epoch for
-// the scan tile states; before the epochs would wrap, the tile states are reset to a
-// value that no epoch matches.
+// Launches `phases` for SCO step `step`.
 int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
   if (step > 0xFFFFFFFFull) return SCO_EINVAL;
-  if (c->epoch + 1u >= 0xFFFFFFu) {
-    HIP_TRY(hipMemsetAsync(at<unsigned long long>(c, c->lay.off_ts), 0xFF,
-                           sizeof(unsigned long long) * c->lay.ntiles, c->stream));
-    c->epoch = 0;
-  }
   if (c->blocks != c->launched_blocks) {
     // the barrier counters count arrivals in groups sized by the grid: start them
     // afresh for another grid size (stream-ordered: no launch is running)
@@ -255,7 +247,6 @@ int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
     c->launched_blocks = c->blocks;
   }
   c->args.step = static_cast<uint32_t>(step);
-  c->args.epoch = ++c->epoch;
   if (c->trace_on) {
     c->args.trace = at<unsigned long long>(c, c->lay.off_trace);
     HIP_TRY(hipMemsetAsync(c->args.trace, 0, sizeof(unsigned long long), c->stream));
@@ -464,13 +455,10 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   if (sco_dev::init_spins(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
                           at<int64_t>(c, L.off_srcbase), dev_init_spins, at<int8_t>(c, L.off_spin), L.G) != hipSuccess)
     return fail(SCO_EHIP);
-  // degrees and scatter cursors are zero between steps; the scan tile states start
-  // with a tag that no launch uses
+  // an empty graph until the first switching (row offsets of zero length)
   if (hipMemsetAsync(at<int32_t>(c, L.off_row), 0, sizeof(int32_t) * (L.G + 1), c->stream) != hipSuccess ||
       hipMemsetAsync(at<int32_t>(c, L.off_deg), 0, sizeof(int32_t) * L.G, c->stream) != hipSuccess ||
-      hipMemsetAsync(at<int32_t>(c, L.off_fill), 0, sizeof(int32_t) * L.G, c->stream) != hipSuccess ||
-      hipMemsetAsync(at<unsigned long long>(c, L.off_ts), 0xFF, sizeof(unsigned long long) * L.ntiles,
-                     c->stream) != hipSuccess)
+      hipMemsetAsync(at<int32_t>(c, L.off_fill), 0, sizeof(int32_t) * L.G, c->stream) != hipSuccess)
     return fail(SCO_EHIP);
 
   StepArgs& a = c->args;
@@ -493,7 +481,7 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   a.rec = at<int4>(c, L.off_rec);
   a.ecount = at<uint32_t>(c, L.off_ecount);
   a.trace = nullptr;
-  a.scan_ts = at<unsigned long long>(c, L.off_ts);
+  a.scan_agg = at<long long>(c, L.off_agg);
   a.G = L.G;
   a.nchunks = static_cast<int32_t>(L.nchunks);
   a.n_chains = n_chains;

@@ -81,7 +81,7 @@ struct StepArgs {
   uint32_t* kw_word;      // [G] colouring state: level:5 | round:9 | colour:9
   int4* rec;              // [G] per-block bucket lists: {site, row start, row end, chain}
   uint32_t* ecount;       // [nchunks] survivors found in each chunk (own region of cap/nchunks)
-  unsigned long long* scan_ts;  // decoupled look-back tile states
+  long long* scan_agg;    // per-tile sums of the degree scan
   unsigned long long* trace;    // [SCO_TRACE_SLOTS] phase marks of block 0
   int64_t G;
   int32_t nchunks, n_chains;
@@ -89,7 +89,6 @@ struct StepArgs {
   int32_t nsw_override;   // >= 0: sweeps for every chain; < 0: each chain's n_sw
   int32_t nsw_max;
   uint32_t step;
-  uint32_t epoch;         // launch counter (tags the scan tile states)
   int32_t tile_limit;     // sites of a KW tile, <= SCO_TILE_MAX (a schedule choice)
 };
 

@@ -1612,8 +1612,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
 // graph; a launch without it checks that the words left by the earlier launches say
 // a complete graph (and colouring) is there.
 template <uint32_t phases>
-__device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, uint32_t epoch, PhaseLds& lds,
-                                          KwShared& ks) {
+__device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, PhaseLds& lds, KwShared& ks) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if constexpr ((phases & PH_SWITCH) != 0) {
@@ -1637,7 +1636,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, uint
     mark(a.trace, 2);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
-    if (!scan_two_pass(a.deg, a.G, a.row_ptr, reinterpret_cast<long long*>(a.scan_ts), lds.list, a.sync))
+    if (!scan_two_pass(a.deg, a.G, a.row_ptr, a.scan_agg, lds.list, a.sync))
       return false;
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 4);
@@ -1695,7 +1694,7 @@ template <uint32_t phases>
 __global__ void __launch_bounds__(kBlock) k_step(const StepArgs a) {
   __shared__ PhaseLds lds;
   __shared__ KwShared ks;
-  step_body<phases>(a, a.step, a.epoch, lds, ks);
+  step_body<phases>(a, a.step, lds, ks);
 }
 
 // =================================================================== observables

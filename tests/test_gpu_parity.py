@@ -224,3 +224,54 @@ def test_schedules_give_identical_chains():
         a.step(t)
     for c in range(len(params)):
         np.testing.assert_array_equal(a.spins(c), ref.spins(c))
+
+
+def test_full_size_graph_and_colouring_properties():
+    """8 chains at L=2304 plus one at L=4096 (59M spins, kappa=2), two steps: for the
+    L=4096 chain and one L=2304 chain, the CSR is symmetric with rows ascending and no
+    duplicates, every displacement index names the bond's displacement, the colouring
+    of the union graph is proper with colours below q, and the observables count the
+    graph and the spins exactly (too large for the CPU reference in a test)."""
+    from paper_1503_03295_amd import SCO
+
+    params = workloads.mixed_precision(precision=0, kappa=2.0)
+    gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
+    log(f"full size: {len(params)} chains, {sum(p['L'] ** 2 for p in params)} spins")
+    gpu.run(0, 2)
+    obs = gpu.observables()
+    for c in (8, 3):
+        L = params[c]["L"]
+        N = L * L
+        rp, col, attr, colors = gpu.graph(c)
+        tab = gpu.tables(c)
+        s = gpu.spins(c)
+        assert rp[0] == 0 and rp[-1] == len(col) == 2 * obs[c]["n_edges"]
+        deg = np.diff(rp)
+        rows = np.repeat(np.arange(N), deg)
+        # rows ascending, no duplicate neighbour, no self bond
+        same_row = rows[1:] == rows[:-1]
+        assert np.all(col[1:][same_row] > col[:-1][same_row])
+        assert np.all(col != rows)
+        # symmetric: (u, w, m) present iff (w, u, m)
+        fwd = rows.astype(np.int64) * N + col
+        bwd = col.astype(np.int64) * N + rows
+        order_f, order_b = np.argsort(fwd), np.argsort(bwd)
+        np.testing.assert_array_equal(fwd[order_f], bwd[order_b])
+        np.testing.assert_array_equal(attr[order_f], attr[order_b])
+        # the displacement of each bond is its table entry (modulo the lattice)
+        dx = (col % L - rows % L) % L
+        dy = (col // L - rows // L) % L
+        tdx, tdy = tab["dx"][attr] % L, tab["dy"][attr] % L
+        assert np.all(((dx == tdx) & (dy == tdy)) | ((dx == (-tdx) % L) & (dy == (-tdy) % L)))
+        # proper colouring of bonds and nearest-neighbour pairs, palette below q
+        assert colors.max() < obs[c]["q"] and obs[c]["colors_used"] <= obs[c]["q"]
+        assert np.all(colors[rows] != colors[col])
+        v = np.arange(N)
+        x, y = v % L, v // L
+        assert np.all(colors[v] != colors[y * L + (x + 1) % L])
+        assert np.all(colors[v] != colors[((y + 1) % L) * L + x])
+        # spins and counters
+        assert obs[c]["M"] == int(s.astype(np.int64).sum())
+        assert obs[c]["attempts"] == 2 * N
+        # union degree bound
+        assert obs[c]["q"] == obs[c]["delta_union"] + 1 and obs[c]["delta_union"] >= 4
