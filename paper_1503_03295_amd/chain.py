@@ -69,11 +69,15 @@ class SCO:
                              ctypes.c_void_p(self.workspace.data_ptr()), self.nbytes, ip,
                              ctypes.c_void_p(self.stream.cuda_stream)), "sco_init")
         self._h = h
+        self._lib = lib()
 
     def __del__(self):
+        # the library object is held by the instance: at interpreter exit the module
+        # globals may already be gone
         h = getattr(self, "_h", None)
-        if h:
-            lib().sco_destroy(h)
+        L = getattr(self, "_lib", None)
+        if h and L is not None:
+            L.sco_destroy(h)
             self._h = None
 
     def close(self) -> None:

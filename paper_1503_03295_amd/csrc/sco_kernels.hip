@@ -30,7 +30,7 @@ constexpr int kWaves = kBlock / 64;
 // Items per thread whose loads are issued together: in colour classes (kBatch) and in
 // scans over sites or survivors (kScan).
 constexpr int kBatch = 3;
-constexpr int kBatchKW = 4;  // in the KW classes
+constexpr int kBatchKW = 1;  // in the KW classes
 constexpr int kScan = 4;
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -1252,7 +1252,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
           if (ok[r]) {
             int v;
             site_of(k, cs[r], v);
-            col[r] = a.color[ks.kc[cs[r]].vbase + v];
+            col[r] = static_cast<int>(a.kw_word[ks.kc[cs[r]].vbase + v] & 0x1FFu);
           }
         }
 #pragma unroll
@@ -1276,63 +1276,78 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       }
     }
     mark(a.trace, 200 + p);
-    for (int cc = qmax - 1; cc >= 0; --cc) {
-      const int b0 = boff[cc], b1 = boff[cc + 1];
-      // every thread of the block runs the same number of iterations; each takes
-      // kBatchKW sites of the class and loads everything they read before deciding any
-      // (sites of one class never read each other's words)
-      for (int kb = b0; kb < b1; kb += kBatchKW * kBlock) {
-        int gs[kBatchKW], cs[kBatchKW], rb[kBatchKW], re[kBatchKW];
-        int nbs[kBatchKW][4];
-        uint32_t wn[kBatchKW][4];
-        bool ok[kBatchKW];
+    // The classes run without a barrier between them.  A pending site of class cc
+    // reads the colours its same-group pending neighbours of higher classes take at
+    // this level and ignores the lower ones (those wait for it), so it decides as soon
+    // as every such word carries this level, and the decision does not depend on when
+    // the words arrived.  Each thread takes the block's list from the top class down,
+    // in increasing position, and a batch of a thread keeps deciding whichever of its
+    // sites are ready and re-reading the words of the others: every wait is on a
+    // higher class, which waits on nothing at the top, so by induction over the
+    // classes every wait ends (all blocks are resident).
+    const int nl = boff[qmax];
+    int cls = qmax - 1;  // class of the thread's current position (only decreases)
+    for (int jb = 0; jb < nl; jb += kBatchKW * kBlock) {
+      int gs[kBatchKW], cs[kBatchKW], cl[kBatchKW], rb[kBatchKW], re[kBatchKW];
+      int nbs[kBatchKW][4];
+      uint32_t wn[kBatchKW][4];
+      bool pend[kBatchKW];
 #pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          const int kx = kb + r * kBlock + tid;
-          ok[r] = kx < b1;
-          gs[r] = 0;
-          cs[r] = 0;
-          rb[r] = re[r] = 0;
+      for (int r = 0; r < kBatchKW; ++r) {
+        const int j = jb + r * kBlock + tid;
+        pend[r] = j < nl;
+        gs[r] = 0;
+        cs[r] = 0;
+        cl[r] = 0;
+        rb[r] = re[r] = 0;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            nbs[r][t] = -1;
-            wn[r][t] = 0;
-          }
-          if (ok[r]) {
-            int v;
-            site_of(k0 + lst[kx], cs[r], v);
-            const KwChain& K = ks.kc[cs[r]];
-            const int32_t vb = static_cast<int32_t>(K.vbase);
-            gs[r] = vb + v;
-            const int y = fdiv(v, K.inv_L), x = v - y * K.L;
-            nn_sites(x, y, K.L, K.periodic, nbs[r]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
-            rb[r] = a.row_ptr[gs[r]];
-            re[r] = a.row_ptr[gs[r] + 1];
-            row_checked(a, rb[r], re[r]);
-          }
+        for (int t = 0; t < 4; ++t) {
+          nbs[r][t] = -1;
+          wn[r][t] = 0;
         }
-        // the first bond partner and its word
-        int pb[kBatchKW];
-        uint32_t wb[kBatchKW];
+        if (pend[r]) {
+          const int kx = nl - 1 - j;
+          while (kx < boff[cls]) --cls;
+          cl[r] = cls;
+          int v;
+          site_of(k0 + lst[kx], cs[r], v);
+          const KwChain& K = ks.kc[cs[r]];
+          const int32_t vb = static_cast<int32_t>(K.vbase);
+          gs[r] = vb + v;
+          const int y = fdiv(v, K.inv_L), x = v - y * K.L;
+          nn_sites(x, y, K.L, K.periodic, nbs[r]);
 #pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-          pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
+          for (int t = 0; t < 4; ++t)
+            if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
+          rb[r] = a.row_ptr[gs[r]];
+          re[r] = a.row_ptr[gs[r] + 1];
+          row_checked(a, rb[r], re[r]);
         }
+      }
+      // the first bond partner and its word
+      int pb[kBatchKW];
+      uint32_t wb[kBatchKW];
+#pragma unroll
+      for (int r = 0; r < kBatchKW; ++r) {
+        const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+        pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
+      }
+#pragma unroll
+      for (int r = 0; r < kBatchKW; ++r) {
+        const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+        wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
+      }
+      int cdone[kBatchKW], rdone[kBatchKW];
+#pragma unroll
+      for (int r = 0; r < kBatchKW; ++r) {
+        cdone[r] = -1;
+        rdone[r] = 0;
+      }
+      for (uint32_t spin = 0;; ++spin) {
+        bool waiting = false;
 #pragma unroll
         for (int r = 0; r < kBatchKW; ++r) {
-          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-          wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
-        }
-        int cdone[kBatchKW], rdone[kBatchKW];
-#pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          cdone[r] = -1;
-          rdone[r] = 0;
-          if (!ok[r]) continue;
+          if (!pend[r]) continue;
           const int32_t g = gs[r];
           const int c = cs[r];
           const KwChain& K = ks.kc[c];
@@ -1341,13 +1356,18 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
           const int grp = fdiv(g - vb, K.inv_q) >> p;
           ColorSet taken;
           int rmax = 0;
+          bool ready = true;
           // neighbour u (chain-local) with word w: same group only; a pending one
-          // counts once decided at this level
+          // counts once decided at this level, and one of a higher class must be
           auto visit = [&](int u, uint32_t w) {
             const int gu = fdiv(u, K.inv_q);
             if ((gu >> p) != grp) return;  // another group at this level
             if ((gu >> (p - 1)) & 1) {     // pending at this level
-              if (static_cast<int>((w >> 18) & 0x1Fu) != p) return;  // undecided: a smaller colour
+              if (static_cast<int>((w >> 18) & 0x1Fu) != p) {
+                const int cu = static_cast<int>(w & 0x1FFu);
+                if (cu > cl[r] && cu < q) ready = false;  // not yet decided
+                return;  // a lower class: decides after this site
+              }
               rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
             }
             taken.add(static_cast<int>(w & 0x1FFu));
@@ -1358,33 +1378,59 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
           if (pb[r] >= 0) visit(pb[r], wb[r]);
           for (int e = rb[r] + 1; e < re[r]; ++e) {
             const int u = a.col[e] - vb;
-            visit(u, ld_relaxed(&a.kw_word[vb + u]));
+            visit(u, spin == 0 ? ld_relaxed(&a.kw_word[vb + u]) : ld_poll(&a.kw_word[vb + u]));
+          }
+          if (!ready) {
+            waiting = true;
+            continue;
           }
           int nc = taken.first_free();
           if (nc >= q) {
             set_flag(a.sync, SCO_FLAG_PALETTE);
             nc = q - 1;
           }
-          a.color[g] = static_cast<uint16_t>(nc);
           st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
                                         static_cast<uint32_t>(nc));
           cdone[r] = c;
           rdone[r] = rmax + 1;
+          pend[r] = false;
         }
+        if (!waiting) break;
+        if (spin > kSpinLimit) set_flag(a.sync, SCO_FLAG_TIMEOUT);
+        if ((spin & 255u) == 255u && timed_out(a.sync)) break;
+        __builtin_amdgcn_s_sleep(1);
+        // re-read the words of the sites still waiting where every XCD sees one value
 #pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
+        for (int r = 0; r < kBatchKW; ++r) {
+          if (!pend[r]) continue;
+          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (nbs[r][t] >= 0) wn[r][t] = ld_poll(&a.kw_word[vb + nbs[r][t]]);
+          if (pb[r] >= 0) wb[r] = ld_poll(&a.kw_word[vb + pb[r]]);
+        }
       }
-      if (p == ks.pmin + 1) mark(a.trace, 300 + 2 * cc);
-      // between the classes of a level only the words change (coherent accesses); the
-      // level ends with a full barrier that also publishes the colours
-      if (!(cc > 0 ? class_barrier(a.sync) : grid_barrier(a.sync))) return false;
-      if (p == ks.pmin + 1) mark(a.trace, 301 + 2 * cc);
+#pragma unroll
+      for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
     }
+    // the level ends with a full barrier that also publishes the colours
+    if (!grid_barrier(a.sync)) return false;
     for (int c = tid; c < nch; c += kBlock)
       if (brounds[c] > 0) atomicMax(&a.st[c].kw_rounds[p], brounds[c]);
     mark(a.trace, 100 + p);
   }
   return true;
+}
+
+// The levels over the whole site space record their decisions only in kw_word; the
+// colours of a block's sweep range are copied out of the words in one coalesced pass
+// (after the full barrier that ends the last level), by the block that sweeps them.
+__device__ __forceinline__ void phase_colour_fill(const StepArgs& a) {
+  const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+  const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
+  const int64_t r1 = min(r0 + S, a.G);
+  for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) a.color[g] = static_cast<uint16_t>(a.kw_word[g] & 0x1FFu);
+  __syncthreads();
 }
 
 // =================================================================== step (3)
@@ -1665,6 +1711,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     if (!grid_barrier(a.sync)) return false;
     // the global levels end with a full barrier (none when every level ran in tiles)
     if (!phase_kw_global(a, ks, lds.list)) return false;
+    if (ks.mmax > ks.pmin) phase_colour_fill(a);
     mark(a.trace, 12);
     if (lead) a.sync->color_valid = 1;
   }
