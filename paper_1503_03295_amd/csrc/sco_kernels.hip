@@ -340,6 +340,16 @@ struct ColorSet {
   }
 };
 
+// The same for palettes of at most 64 colours (every colour stored is below q).
+struct ColorSet64 {
+  uint64_t w = 0;
+  __device__ __forceinline__ void add(int c) { w |= 1ull << (c & 63); }
+  __device__ __forceinline__ void add_if(bool on, int c) { w |= on ? 1ull << (c & 63) : 0ull; }
+  __device__ __forceinline__ int first_free() const {
+    return ~w ? __ffsll(static_cast<unsigned long long>(~w)) - 1 : 64;
+  }
+};
+
 // Phase marks of block 0 (wall clock), for attributing the time of the persistent
 // kernel: trace[0] = count, then (id, time) pairs.
 __device__ __forceinline__ void mark(unsigned long long* trace, uint32_t id) {
@@ -1114,56 +1124,87 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       }
       __syncthreads();
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 80 + p);
-      for (int cc = q - 1; cc >= 0; --cc) {
+      // The classes run from the top down with no barrier between them: a site
+      // decides as soon as its same-group pending neighbours of higher classes have
+      // (their LDS words carry a round), re-reading the words while it waits; lower
+      // classes are ignored and wait for it.  Each thread takes the list from the top
+      // class down in increasing position, so every wait is on an earlier position of
+      // a higher class and, by induction over the classes, ends.
+      auto run_classes = [&](auto set_tag) {
+        using Set = decltype(set_tag);
+        volatile uint16_t* const vcr = t_cr;
         int tmax = 0;
-        for (int k = t_off[cc] + threadIdx.x; k < t_off[cc + 1]; k += kBlock) {
-          const int i = t_list[k];
+        int cls = q - 1;  // class of the thread's current position (only decreases)
+        for (int j = tid; j < npend; j += kBlock) {
+          const int kx = npend - 1 - j;
+          while (kx < t_off[cls]) --cls;
+          const int i = t_list[kx];
           const int grp = div16(i, mq) >> p;
-          ColorSet taken;
-          int rmax = 0;
-          // neighbour j (tile index, -1 for none): same group only; a pending one
-          // counts once decided.  Branch-free, so the LDS reads of all neighbours are
-          // issued together.
-          auto visit = [&](int j) {
-            const bool in = j >= 0 && j < n;  // outside the tile: another group
-            const int jj = in ? j : i;
-            const int w = t_cr[jj];
-            const int gj = div16(jj, mq);
-            const bool pend = (gj >> (p - 1)) & 1;
-            const int rj = w >> 8;
-            const bool on = in && (gj >> p) == grp && (!pend || rj != 0);
-            rmax = max(rmax, on && pend ? rj : 0);
-            taken.add_if(on, w & 0xFF);
-          };
           const int t = x0 + i, dy = div16(t, mL);
           int nb[4];
           nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) visit(nb[u] >= 0 ? nb[u] - v0 : -1);
+          int e0 = 0, e1 = 0, g0 = 0, g1 = 0;  // in-tile bonds in LDS, or the row in memory
           const uint32_t mw = t_bmask[i >> 5];
           if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
             const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
-            const int e1 = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
-            if (e1 <= kAdjCap) {
-              for (int e = t_boff[r]; e < e1; ++e) visit(t_adj[e]);
+            const int eb = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
+            if (eb <= kAdjCap) {
+              e0 = t_boff[r];
+              e1 = eb;
             } else {
-              int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
-              row_checked(a, r0, r1);
-              for (int e = r0; e < r1; ++e) visit(a.col[e] - gt0);
+              g0 = a.row_ptr[gt0 + i];
+              g1 = a.row_ptr[gt0 + i + 1];
+              row_checked(a, g0, g1);
             }
           }
-          int nc = taken.first_free();
-          if (nc >= q) {
-            set_flag(a.sync, SCO_FLAG_PALETTE);
-            nc = q - 1;
+          for (uint32_t spin = 0;; ++spin) {
+            Set taken;
+            int rmax = 0;
+            bool ready = true;
+            // neighbour j (tile index, -1 for none): same group only; a pending one
+            // counts once decided and one of a higher class must be.  Branch-free, so
+            // the LDS reads of all neighbours are issued together.
+            auto visit = [&](int jn) {
+              const bool in = jn >= 0 && jn < n;  // outside the tile: another group
+              const int jj = in ? jn : i;
+              const int w = vcr[jj];
+              const int gj = div16(jj, mq);
+              const bool pend = (gj >> (p - 1)) & 1;
+              const int rj = w >> 8;
+              const bool same = in && (gj >> p) == grp;
+              const bool on = same && (!pend || rj != 0);
+              const int cj = w & 0xFF;
+              ready = ready && !(same && pend && rj == 0 && cj > cls && cj < q);
+              rmax = max(rmax, on && pend ? rj : 0);
+              taken.add_if(on, cj);
+            };
+#pragma unroll
+            for (int u = 0; u < 4; ++u) visit(nb[u] >= 0 ? nb[u] - v0 : -1);
+            for (int e = e0; e < e1; ++e) visit(t_adj[e]);
+            for (int e = g0; e < g1; ++e) visit(a.col[e] - gt0);
+            if (ready) {
+              int nc = taken.first_free();
+              if (nc >= q) {
+                set_flag(a.sync, SCO_FLAG_PALETTE);
+                nc = q - 1;
+              }
+              vcr[i] = static_cast<uint16_t>(nc | ((rmax + 1) << 8));
+              tmax = max(tmax, rmax + 1);
+              break;
+            }
+            if (spin > kSpinLimit) {
+              set_flag(a.sync, SCO_FLAG_TIMEOUT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
           }
-          t_cr[i] = static_cast<uint16_t>(nc | ((rmax + 1) << 8));
-          tmax = max(tmax, rmax + 1);
         }
         tmax = wave_max(tmax);
         if (lane == 0 && tmax > 0) atomicMax(&t_rounds, tmax);
-        __syncthreads();
-      }
+      };
+      if (q <= 64) run_classes(ColorSet64{});
+      else run_classes(ColorSet{});
+      __syncthreads();
       if (threadIdx.x == 0 && t_rounds > 0) atomicMax(&a.st[c].kw_rounds[p], t_rounds);
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 40 + p);
     }
