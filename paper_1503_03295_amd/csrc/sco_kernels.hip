@@ -73,7 +73,7 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // exact floor(v / d) for 0 <= v < 2^31, 1 <= d < 2^20, via a double reciprocal:
 // (v + 1/2) / d is at least 1/(2d) away from an integer, while the two roundings
 // move the product by at most 2^31 2^-52 = 2^-21.
-__device__ __forceinline__ int fdiv(int v, double inv_d) {
+__device__ __forceinline__ int idiv_fp(int v, double inv_d) {
   return static_cast<int>((static_cast<double>(v) + 0.5) * inv_d);
 }
 
@@ -442,7 +442,7 @@ __device__ __forceinline__ bool owner_take(const StepArgs& a, const Desc& desc_o
     o.g = g;
     o.v = v;
     o.c = c;
-    o.y = fdiv(v, d.inv_L);
+    o.y = idiv_fp(v, d.inv_L);
     o.x = v - o.y * d.L;
     o.pos = -1;
     o.k = 0;
@@ -816,7 +816,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
           col[b + 1] = kc;
           attr[b + 1] = ka;
         }
-        const int y = fdiv(v, d.inv_L), x = v - y * d.L;
+        const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
         int nb[4];
         nn_sites(x, y, d.L, d.periodic, nb);
         udeg = rowlen;
@@ -987,7 +987,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     // tile indices and x0 + i are below 2^16, so the divisions by q, L and the
     // half-group sizes are exact multiply-highs
     const uint32_t mq = magic16(static_cast<uint32_t>(q)), mL = magic16(static_cast<uint32_t>(L));
-    const int y0 = fdiv(v0, K.inv_L), x0 = v0 - y0 * L;
+    const int y0 = idiv_fp(v0, K.inv_L), x0 = v0 - y0 * L;
     const int nw = (n + 31) >> 5;
     if (P > 0) {
       // 1. in-tile partner counts (held in cr until the colours start) and the mask of
@@ -1327,133 +1327,138 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     // higher class, which waits on nothing at the top, so by induction over the
     // classes every wait ends (all blocks are resident).
     const int nl = boff[qmax];
-    int cls = qmax - 1;  // class of the thread's current position (only decreases)
-    for (int jb = 0; jb < nl; jb += kBatchKW * kBlock) {
-      int gs[kBatchKW], cs[kBatchKW], cl[kBatchKW], rb[kBatchKW], re[kBatchKW];
-      int nbs[kBatchKW][4];
-      uint32_t wn[kBatchKW][4];
-      bool pend[kBatchKW];
-#pragma unroll
-      for (int r = 0; r < kBatchKW; ++r) {
-        const int j = jb + r * kBlock + tid;
-        pend[r] = j < nl;
-        gs[r] = 0;
-        cs[r] = 0;
-        cl[r] = 0;
-        rb[r] = re[r] = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          nbs[r][t] = -1;
-          wn[r][t] = 0;
-        }
-        if (pend[r]) {
-          const int kx = nl - 1 - j;
-          while (kx < boff[cls]) --cls;
-          cl[r] = cls;
-          int v;
-          site_of(k0 + lst[kx], cs[r], v);
-          const KwChain& K = ks.kc[cs[r]];
-          const int32_t vb = static_cast<int32_t>(K.vbase);
-          gs[r] = vb + v;
-          const int y = fdiv(v, K.inv_L), x = v - y * K.L;
-          nn_sites(x, y, K.L, K.periodic, nbs[r]);
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
-          rb[r] = a.row_ptr[gs[r]];
-          re[r] = a.row_ptr[gs[r] + 1];
-          row_checked(a, rb[r], re[r]);
-        }
-      }
-      // the first bond partner and its word
-      int pb[kBatchKW];
-      uint32_t wb[kBatchKW];
-#pragma unroll
-      for (int r = 0; r < kBatchKW; ++r) {
-        const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-        pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
-      }
-#pragma unroll
-      for (int r = 0; r < kBatchKW; ++r) {
-        const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-        wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
-      }
-      int cdone[kBatchKW], rdone[kBatchKW];
-#pragma unroll
-      for (int r = 0; r < kBatchKW; ++r) {
-        cdone[r] = -1;
-        rdone[r] = 0;
-      }
-      for (uint32_t spin = 0;; ++spin) {
-        bool waiting = false;
+    auto run_level = [&](auto set_tag) {
+      using Set = decltype(set_tag);
+      int cls = qmax - 1;  // class of the thread's current position (only decreases)
+      for (int jb = 0; jb < nl; jb += kBatchKW * kBlock) {
+        int gs[kBatchKW], cs[kBatchKW], cl[kBatchKW], rb[kBatchKW], re[kBatchKW];
+        int nbs[kBatchKW][4];
+        uint32_t wn[kBatchKW][4];
+        bool pend[kBatchKW];
 #pragma unroll
         for (int r = 0; r < kBatchKW; ++r) {
-          if (!pend[r]) continue;
-          const int32_t g = gs[r];
-          const int c = cs[r];
-          const KwChain& K = ks.kc[c];
-          const int q = K.q;
-          const int32_t vb = static_cast<int32_t>(K.vbase);
-          const int grp = fdiv(g - vb, K.inv_q) >> p;
-          ColorSet taken;
-          int rmax = 0;
-          bool ready = true;
-          // neighbour u (chain-local) with word w: same group only; a pending one
-          // counts once decided at this level, and one of a higher class must be
-          auto visit = [&](int u, uint32_t w) {
-            const int gu = fdiv(u, K.inv_q);
-            if ((gu >> p) != grp) return;  // another group at this level
-            if ((gu >> (p - 1)) & 1) {     // pending at this level
-              if (static_cast<int>((w >> 18) & 0x1Fu) != p) {
-                const int cu = static_cast<int>(w & 0x1FFu);
-                if (cu > cl[r] && cu < q) ready = false;  // not yet decided
-                return;  // a lower class: decides after this site
-              }
-              rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
-            }
-            taken.add(static_cast<int>(w & 0x1FFu));
-          };
+          const int j = jb + r * kBlock + tid;
+          pend[r] = j < nl;
+          gs[r] = 0;
+          cs[r] = 0;
+          cl[r] = 0;
+          rb[r] = re[r] = 0;
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (nbs[r][t] >= 0) visit(nbs[r][t], wn[r][t]);
-          if (pb[r] >= 0) visit(pb[r], wb[r]);
-          for (int e = rb[r] + 1; e < re[r]; ++e) {
-            const int u = a.col[e] - vb;
-            visit(u, spin == 0 ? ld_relaxed(&a.kw_word[vb + u]) : ld_poll(&a.kw_word[vb + u]));
+          for (int t = 0; t < 4; ++t) {
+            nbs[r][t] = -1;
+            wn[r][t] = 0;
           }
-          if (!ready) {
-            waiting = true;
-            continue;
+          if (pend[r]) {
+            const int kx = nl - 1 - j;
+            while (kx < boff[cls]) --cls;
+            cl[r] = cls;
+            int v;
+            site_of(k0 + lst[kx], cs[r], v);
+            const KwChain& K = ks.kc[cs[r]];
+            const int32_t vb = static_cast<int32_t>(K.vbase);
+            gs[r] = vb + v;
+            const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
+            nn_sites(x, y, K.L, K.periodic, nbs[r]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
+            rb[r] = a.row_ptr[gs[r]];
+            re[r] = a.row_ptr[gs[r] + 1];
+            row_checked(a, rb[r], re[r]);
           }
-          int nc = taken.first_free();
-          if (nc >= q) {
-            set_flag(a.sync, SCO_FLAG_PALETTE);
-            nc = q - 1;
-          }
-          st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
-                                        static_cast<uint32_t>(nc));
-          cdone[r] = c;
-          rdone[r] = rmax + 1;
-          pend[r] = false;
         }
-        if (!waiting) break;
-        if (spin > kSpinLimit) set_flag(a.sync, SCO_FLAG_TIMEOUT);
-        if ((spin & 255u) == 255u && timed_out(a.sync)) break;
-        __builtin_amdgcn_s_sleep(1);
-        // re-read the words of the sites still waiting where every XCD sees one value
+        // the first bond partner and its word
+        int pb[kBatchKW];
+        uint32_t wb[kBatchKW];
 #pragma unroll
         for (int r = 0; r < kBatchKW; ++r) {
-          if (!pend[r]) continue;
           const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (nbs[r][t] >= 0) wn[r][t] = ld_poll(&a.kw_word[vb + nbs[r][t]]);
-          if (pb[r] >= 0) wb[r] = ld_poll(&a.kw_word[vb + pb[r]]);
+          pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
         }
-      }
 #pragma unroll
-      for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
-    }
+        for (int r = 0; r < kBatchKW; ++r) {
+          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+          wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
+        }
+        int cdone[kBatchKW], rdone[kBatchKW];
+#pragma unroll
+        for (int r = 0; r < kBatchKW; ++r) {
+          cdone[r] = -1;
+          rdone[r] = 0;
+        }
+        for (uint32_t spin = 0;; ++spin) {
+          bool waiting = false;
+#pragma unroll
+          for (int r = 0; r < kBatchKW; ++r) {
+            if (!pend[r]) continue;
+            const int32_t g = gs[r];
+            const int c = cs[r];
+            const KwChain& K = ks.kc[c];
+            const int q = K.q;
+            const int32_t vb = static_cast<int32_t>(K.vbase);
+            const int grp = idiv_fp(g - vb, K.inv_q) >> p;
+            Set taken;
+            int rmax = 0;
+            bool ready = true;
+            // neighbour u (chain-local) with word w: same group only; a pending one
+            // counts once decided at this level, and one of a higher class must be
+            auto visit = [&](int u, uint32_t w) {
+              const int gu = idiv_fp(u, K.inv_q);
+              if ((gu >> p) != grp) return;  // another group at this level
+              if ((gu >> (p - 1)) & 1) {     // pending at this level
+                if (static_cast<int>((w >> 18) & 0x1Fu) != p) {
+                  const int cu = static_cast<int>(w & 0x1FFu);
+                  if (cu > cl[r] && cu < q) ready = false;  // not yet decided
+                  return;  // a lower class: decides after this site
+                }
+                rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
+              }
+              taken.add(static_cast<int>(w & 0x1FFu));
+            };
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (nbs[r][t] >= 0) visit(nbs[r][t], wn[r][t]);
+            if (pb[r] >= 0) visit(pb[r], wb[r]);
+            for (int e = rb[r] + 1; e < re[r]; ++e) {
+              const int u = a.col[e] - vb;
+              visit(u, spin == 0 ? ld_relaxed(&a.kw_word[vb + u]) : ld_poll(&a.kw_word[vb + u]));
+            }
+            if (!ready) {
+              waiting = true;
+              continue;
+            }
+            int nc = taken.first_free();
+            if (nc >= q) {
+              set_flag(a.sync, SCO_FLAG_PALETTE);
+              nc = q - 1;
+            }
+            st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
+                                          static_cast<uint32_t>(nc));
+            cdone[r] = c;
+            rdone[r] = rmax + 1;
+            pend[r] = false;
+          }
+          if (!waiting) break;
+          if (spin > kSpinLimit) set_flag(a.sync, SCO_FLAG_TIMEOUT);
+          if ((spin & 255u) == 255u && timed_out(a.sync)) break;
+          __builtin_amdgcn_s_sleep(1);
+          // re-read the words of the sites still waiting where every XCD sees one value
+#pragma unroll
+          for (int r = 0; r < kBatchKW; ++r) {
+            if (!pend[r]) continue;
+            const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (nbs[r][t] >= 0) wn[r][t] = ld_poll(&a.kw_word[vb + nbs[r][t]]);
+            if (pb[r] >= 0) wb[r] = ld_poll(&a.kw_word[vb + pb[r]]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
+      }
+    };
+    if (qmax <= 64) run_level(ColorSet64{});
+    else run_level(ColorSet{});
     // the level ends with a full barrier that also publishes the colours
     if (!grid_barrier(a.sync)) return false;
     for (int c = tid; c < nch; c += kBlock)
@@ -1569,7 +1574,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
             live[r] = s < nsw;
             if (live[r]) {
               const int v = static_cast<int>(gs[r] - d.vbase);
-              const int y = fdiv(v, d.inv_L), x = v - y * d.L;
+              const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
               int nb[4];
               nn_sites(x, y, d.L, d.periodic, nb);
 #pragma unroll
