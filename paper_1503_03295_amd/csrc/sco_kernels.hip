@@ -793,6 +793,21 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
         }
       }
     }
+    // rows of up to kRowReg entries (nearly all) are read in one round for all kScan
+    // rows, sorted in registers and written back; longer ones are sorted in place
+    constexpr int kRowReg = 4;
+    int kc[kScan][kRowReg], ka[kScan][kRowReg];
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) {
+      row_checked(a, r0[r], r1[r]);
+      const int len = r1[r] - r0[r];
+#pragma unroll
+      for (int i = 0; i < kRowReg; ++i) {
+        const bool in = len <= kRowReg && i < len;
+        kc[r][i] = in ? a.col[r0[r] + i] : INT32_MAX;
+        ka[r][i] = in ? a.attr[r0[r] + i] : 0;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < kScan; ++r) {
       int udeg = 0, rowlen = 0;
@@ -800,33 +815,61 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
         const ChainDesc& d = a.cd[cs[r]];
         const int64_t g = (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x;
         const int v = static_cast<int>(g - d.vbase);
-        int q0 = r0[r], q1 = r1[r];
-        row_checked(a, q0, q1);
+        const int q0 = r0[r], q1 = r1[r];
         rowlen = q1 - q0;
-        int32_t* __restrict__ col = a.col;
-        int32_t* __restrict__ attr = a.attr;
-        for (int q = q0 + 1; q < q1; ++q) {
-          const int32_t kc = col[q], ka = attr[q];
-          int b = q - 1;
-          while (b >= q0 && col[b] > kc) {
-            col[b + 1] = col[b];
-            attr[b + 1] = attr[b];
-            --b;
-          }
-          col[b + 1] = kc;
-          attr[b + 1] = ka;
-        }
         const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
         int nb[4];
         nn_sites(x, y, d.L, d.periodic, nb);
         udeg = rowlen;
+        if (rowlen <= kRowReg) {
+          // adjacent exchanges on strictly greater keys: a stable sort (padding last)
+          auto cx = [&](int i) {
+            const bool sw = kc[r][i] > kc[r][i + 1];
+            const int c0 = kc[r][i], a0 = ka[r][i];
+            kc[r][i] = sw ? kc[r][i + 1] : c0;
+            ka[r][i] = sw ? ka[r][i + 1] : a0;
+            kc[r][i + 1] = sw ? c0 : kc[r][i + 1];
+            ka[r][i + 1] = sw ? a0 : ka[r][i + 1];
+          };
+          cx(0); cx(1); cx(2); cx(0); cx(1); cx(0);
+          if (rowlen > 1)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (nb[t] < 0) continue;
-          const int32_t gu = static_cast<int32_t>(d.vbase + nb[t]);
-          bool dup = false;
-          for (int b = q0; b < q1; ++b) dup |= (col[b] == gu);
-          udeg += dup ? 0 : 1;
+            for (int i = 0; i < kRowReg; ++i)
+              if (i < rowlen) {
+                a.col[q0 + i] = kc[r][i];
+                a.attr[q0 + i] = ka[r][i];
+              }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (nb[t] < 0) continue;
+            const int32_t gu = static_cast<int32_t>(d.vbase + nb[t]);
+            bool dup = false;
+#pragma unroll
+            for (int i = 0; i < kRowReg; ++i) dup |= (kc[r][i] == gu);
+            udeg += dup ? 0 : 1;
+          }
+        } else {
+          int32_t* __restrict__ col = a.col;
+          int32_t* __restrict__ attr = a.attr;
+          for (int q = q0 + 1; q < q1; ++q) {
+            const int32_t kq = col[q], aq = attr[q];
+            int b = q - 1;
+            while (b >= q0 && col[b] > kq) {
+              col[b + 1] = col[b];
+              attr[b + 1] = attr[b];
+              --b;
+            }
+            col[b + 1] = kq;
+            attr[b + 1] = aq;
+          }
+          bool dup[4] = {false, false, false, false};
+          for (int b = q0; b < q1; ++b) {
+            const int32_t cb = col[b];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dup[t] |= nb[t] >= 0 && cb == static_cast<int32_t>(d.vbase + nb[t]);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) udeg += (nb[t] >= 0 && !dup[t]) ? 1 : 0;
         }
       }
       const int c = ok[r] ? cs[r] : -1;
