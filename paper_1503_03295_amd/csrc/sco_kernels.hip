@@ -456,9 +456,42 @@ __device__ __forceinline__ bool owner_take(const StepArgs& a, const Desc& desc_o
   return false;
 }
 
+// The first kSwC entries of a chain's cumulative couplings C and displacements hd,
+// and a guide of kSwGuide buckets, staged in LDS for the switching of a block whose
+// chunks all belong to that chain; nearly every candidate falls among them.  KL = 0:
+// everything is read from global memory.
+constexpr int kSwC = 8192;
+constexpr int kSwGuide = 1 << 12;
+struct SwitchTables {
+  const double* C;       // C_0 .. C_{KL-1}
+  const uint32_t* hd;    // hd_0 .. hd_{KL-1}
+  const int32_t* guide;  // guide[b] = first m with C_m >= b C_top / kSwGuide, b = 0..kSwGuide
+  int KL;
+  double guide_inv;      // kSwGuide / C_top
+  __device__ __forceinline__ double c_at(const ChainDesc& d, int m) const { return m < KL ? C[m] : d.C[m]; }
+  __device__ __forceinline__ uint32_t hd_at(const ChainDesc& d, int m) const { return m < KL ? hd[m] : d.hd[m]; }
+};
+
 // First table index m > pos with C_m >= target (guide-table bracket, then binary
-// search over the FP64 cumulative couplings).
-__device__ __forceinline__ int table_search(const ChainDesc& d, double target, int pos) {
+// search over the FP64 cumulative couplings).  The LDS bracket is used when it lies
+// inside the staged entries; both brackets contain the answer, so the result is the
+// same either way.
+__device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTables& tb, double target, int pos) {
+  if (tb.KL > 0) {
+    int b = static_cast<int>(target * tb.guide_inv);
+    b = b < 0 ? 0 : (b > kSwGuide ? kSwGuide : b);
+    const int hi0 = (b + 2 <= kSwGuide) ? tb.guide[b + 2] : d.K - 1;
+    if (hi0 < tb.KL) {
+      int lo = tb.guide[b > 0 ? b - 1 : 0], hi = hi0;
+      lo = lo > pos + 1 ? lo : pos + 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tb.C[mid] >= target) hi = mid;
+        else lo = mid + 1;
+      }
+      return lo;
+    }
+  }
   const double* __restrict__ C = d.C;
   const int K = d.K, NB = d.nguide;
   int b = static_cast<int>(target * d.guide_inv);
@@ -474,14 +507,15 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, double target, i
   return lo;
 }
 
-// One draw of a live owner: the next candidate (j, m) and whether it survives.  The
-// owner ends when the target passes C_top or the table is exhausted.  With precision
+// One draw of a live owner: the next candidate (table entry m, partner j, -1 when the
+// displacement leaves an open lattice, and the draw index kc); false when the owner
+// ends instead (the target passes C_top or the table is exhausted).  With precision
 // 1 the exponential gap is computed in FP32; the FP64 outcome is certain unless the
 // target lies within `tol` of C_top or of the table values it was compared with, and
 // then the gap is recomputed in FP64 (counted in `rechecks`).
 template <class Desc>
-__device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_of, uint32_t step, Owner& o, int& j,
-                                           int& m) {
+__device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& desc_of, const SwitchTables& tb,
+                                                uint32_t step, Owner& o, int& j, int& m, uint32_t& kc) {
   const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -500,7 +534,6 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_o
     whi = o.shi;
   }
   const double u1 = unit52(wlo, whi);
-  const double* __restrict__ C = d.C;
   bool done = false;
   if (d.precision == 1) {
     // -log u rounded through FP32 (u to float: 2^-24 relative; logf: about one ulp;
@@ -514,8 +547,8 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_o
       return false;
     }
     if (target + tol <= d.C_top) {
-      m = table_search(d, target, o.pos);
-      done = C[m] >= target + tol && (m == o.pos + 1 || C[m - 1] < target - tol);
+      m = table_search(d, tb, target, o.pos);
+      done = tb.c_at(d, m) >= target + tol && (m == o.pos + 1 || tb.c_at(d, m - 1) < target - tol);
     }
     if (!done) atomicAdd(&a.st[o.c].rechecks, 1ull);  // rare: one atomic each
   }
@@ -525,24 +558,31 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_o
       o.live = false;
       return false;
     }
-    m = table_search(d, target, o.pos);
+    m = table_search(d, tb, target, o.pos);
   }
-  const uint32_t p = d.hd[m];
+  const uint32_t p = tb.hd_at(d, m);
   const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
   j = partner_of(o.x, o.y, dx, dy, d.L, d.periodic);
-  bool found = false;
-  if (j >= 0) {
-    found = o.si != a.spin[d.vbase + j];
-    if (!found && !d.hard) {
-      const W4 t = philox10(step, static_cast<uint32_t>(o.v), o.k, SCO_TAG_TH, d.seed, d.chain_id);
-      found = unit52(t.x, t.y) < d.theta[m];
-    }
-  }
+  kc = o.k;
   o.pos = m;
-  o.Cpos = C[m];
+  o.Cpos = tb.c_at(d, m);
   ++o.k;
-  return found;
+  return true;
 }
+
+// Whether candidate (j, m, kc) of owner o survives, given the partner's spin sj:
+// antiparallel spins always, parallel ones (kappa > 1) with probability theta_m.
+template <class Desc>
+__device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t step, const Owner& o, int j, int m,
+                                               uint32_t kc, int sj) {
+  if (j < 0) return false;
+  const ChainDesc& d = desc_of(o.c);
+  if (o.si != sj) return true;
+  if (d.hard) return false;
+  const W4 t = philox10(step, static_cast<uint32_t>(o.v), kc, SCO_TAG_TH, d.seed, d.chain_id);
+  return unit52(t.x, t.y) < d.theta[m];
+}
+
 
 // One thread per owner site.  Candidate bonds of owner v: the table intervals
 // (C_{m-1}, C_m] hit by a Poisson process of rate (kappa+1) beta run from C = 0,
@@ -556,7 +596,7 @@ __device__ __forceinline__ bool owner_draw(const StepArgs& a, const Desc& desc_o
 // range in flight and starts the next one as soon as one ends, so a wave is not held
 // by its slowest owner.  Survivors go to the block's region (one LDS atomic per wave
 // and append); its count is written to the entry of the range's first chunk.
-__device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
+__device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, int32_t* lds_raw) {
   __shared__ uint32_t s_count;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
@@ -583,24 +623,28 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
         a.eb[e] = gj;
         a.em[e] = m;
         a.er[e] = ns++;
-        atomicAdd(&a.deg[g], 1);
-        atomicAdd(&a.deg[gj], 1);
       } else {
         set_flag(a.sync, SCO_FLAG_OVERFLOW);
       }
     }
     return ns;
   };
-  auto run = [&](const auto& desc_of) {
+  auto run = [&](const auto& desc_of, const SwitchTables& tb) {
     int next = ch0;
     Owner A, B;
     A.ns = B.ns = 0;
     owner_take(a, desc_of, A, next, ch1);
     owner_take(a, desc_of, B, next, ch1);
     while (__ballot(A.live || B.live) != 0) {
+      // both candidates first, then both partner spins in flight together
       int jA = -1, mA = 0, jB = -1, mB = 0;
-      const bool fA = A.live && owner_draw(a, desc_of, step, A, jA, mA);
-      const bool fB = B.live && owner_draw(a, desc_of, step, B, jB, mB);
+      uint32_t kA = 0, kB = 0;
+      const bool cA = A.live && owner_candidate(a, desc_of, tb, step, A, jA, mA, kA);
+      const bool cB = B.live && owner_candidate(a, desc_of, tb, step, B, jB, mB, kB);
+      const int sA = cA && jA >= 0 ? a.spin[desc_of(A.c).vbase + jA] : 0;
+      const int sB = cB && jB >= 0 ? a.spin[desc_of(B.c).vbase + jB] : 0;
+      const bool fA = cA && owner_survives(desc_of, step, A, jA, mA, kA, sA);
+      const bool fB = cB && owner_survives(desc_of, step, B, jB, mB, kB, sB);
       A.ns = append(fA, A.g, A.c, jA, mA, A.ns);
       B.ns = append(fB, B.g, B.c, jB, mB, B.ns);
       // an ended owner's survivor count starts its row's cursor for the partners
@@ -622,14 +666,36 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step) {
     const int c_lo = a.chunk_chain[ch0], c_hi = a.chunk_chain[ch1 - 1];
     if (c_lo == c_hi) {
       const ChainDesc& d0 = a.cd[c_lo];
-      run([&](int) -> const ChainDesc& { return d0; });
+      // the chain's table head in LDS (the guide every nguide / kSwGuide-th bucket)
+      double* lC = reinterpret_cast<double*>(lds_raw);
+      uint32_t* lhd = reinterpret_cast<uint32_t*>(lC + kSwC);
+      int32_t* lg = reinterpret_cast<int32_t*>(lhd + kSwC);
+      const int gs = d0.nguide / kSwGuide;
+      const int KL = (gs >= 1 && gs * kSwGuide == d0.nguide) ? min(d0.K, kSwC) : 0;
+      for (int i = threadIdx.x; i < KL; i += kBlock) {
+        lC[i] = d0.C[i];
+        lhd[i] = d0.hd[i];
+      }
+      if (KL > 0)
+        for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = d0.guide[b * gs];
+      __syncthreads();
+      const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs};
+      run([&](int) -> const ChainDesc& { return d0; }, tb);
     } else {
-      run([&](int c) -> const ChainDesc& { return a.cd[c]; });
+      const SwitchTables tb{nullptr, nullptr, nullptr, 0, 0.0};
+      run([&](int c) -> const ChainDesc& { return a.cd[c]; }, tb);
     }
   }
   __syncthreads();
+  // the degrees, from the block's survivor list: the atomics are issued after the
+  // draws, so no load of the draw loop waits behind them
+  const uint32_t ne = min(s_count, cap_blk);
+  for (uint32_t e = threadIdx.x; e < ne; e += kBlock) {
+    atomicAdd(&a.deg[a.ea[e_base + e]], 1);
+    atomicAdd(&a.deg[a.eb[e_base + e]], 1);
+  }
   if (threadIdx.x == 0)
-    for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? min(s_count, cap_blk) : 0u;
+    for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? ne : 0u;
   __syncthreads();
 }
 
@@ -992,7 +1058,10 @@ struct TileLds {
 };
 constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
 static_assert(kListCap >= kScanLds, "the scan stages a padded tile in the phase LDS");
-union PhaseLds {
+static_assert(static_cast<int>(sizeof(int32_t)) * kListCap >=
+                  kSwC * static_cast<int>(sizeof(double) + sizeof(uint32_t)) + (kSwGuide + 1) * static_cast<int>(sizeof(int32_t)),
+              "the switching stages its table head in the phase LDS");
+union alignas(16) PhaseLds {
   TileLds tile;
   int32_t list[kListCap];
 };
@@ -1175,7 +1244,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       // a higher class and, by induction over the classes, ends.
       auto run_classes = [&](auto set_tag) {
         using Set = decltype(set_tag);
-        volatile uint16_t* const vcr = t_cr;
+        // the words are read and written with workgroup-scope atomics: every wait sees
+        // the other waves' decisions, and the accesses stay LDS instructions
+        auto cr_ld = [&](int k) -> int { return __hip_atomic_load(&t_cr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
         int tmax = 0;
         int cls = q - 1;  // class of the thread's current position (only decreases)
         for (int j = tid; j < npend; j += kBlock) {
@@ -1210,7 +1281,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
             auto visit = [&](int jn) {
               const bool in = jn >= 0 && jn < n;  // outside the tile: another group
               const int jj = in ? jn : i;
-              const int w = vcr[jj];
+              const int w = cr_ld(jj);
               const int gj = div16(jj, mq);
               const bool pend = (gj >> (p - 1)) & 1;
               const int rj = w >> 8;
@@ -1231,7 +1302,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
                 set_flag(a.sync, SCO_FLAG_PALETTE);
                 nc = q - 1;
               }
-              vcr[i] = static_cast<uint16_t>(nc | ((rmax + 1) << 8));
+              __hip_atomic_store(&t_cr[i], static_cast<uint16_t>(nc | ((rmax + 1) << 8)), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
               tmax = max(tmax, rmax + 1);
               break;
             }
@@ -1767,7 +1839,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     }
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 1);
-    phase_switch(a, step);
+    phase_switch(a, step, lds.list);
     mark(a.trace, 2);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
