@@ -86,6 +86,13 @@ __device__ __forceinline__ int div16(int i, uint32_t m) {
   return static_cast<int>(__umulhi(static_cast<uint32_t>(i), m));
 }
 
+// A read through a pointer known to address global memory (tables whose pointers
+// are themselves read from memory would otherwise be read with flat instructions).
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)(p);
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -468,8 +475,10 @@ struct SwitchTables {
   const int32_t* guide;  // guide[b] = first m with C_m >= b C_top / kSwGuide, b = 0..kSwGuide
   int KL;
   double guide_inv;      // kSwGuide / C_top
-  __device__ __forceinline__ double c_at(const ChainDesc& d, int m) const { return m < KL ? C[m] : d.C[m]; }
-  __device__ __forceinline__ uint32_t hd_at(const ChainDesc& d, int m) const { return m < KL ? hd[m] : d.hd[m]; }
+  __device__ __forceinline__ double c_at(const ChainDesc& d, int m) const { return m < KL ? C[m] : ld_global(&d.C[m]); }
+  __device__ __forceinline__ uint32_t hd_at(const ChainDesc& d, int m) const {
+    return m < KL ? hd[m] : ld_global(&d.hd[m]);
+  }
 };
 
 // First table index m > pos with C_m >= target (guide-table bracket, then binary
@@ -496,12 +505,12 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTabl
   const int K = d.K, NB = d.nguide;
   int b = static_cast<int>(target * d.guide_inv);
   b = b < 0 ? 0 : (b > NB ? NB : b);
-  int lo = d.guide[b > 0 ? b - 1 : 0];
-  int hi = (b + 2 <= NB) ? d.guide[b + 2] : K - 1;
+  int lo = ld_global(&d.guide[b > 0 ? b - 1 : 0]);
+  int hi = (b + 2 <= NB) ? ld_global(&d.guide[b + 2]) : K - 1;
   lo = lo > pos + 1 ? lo : pos + 1;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (C[mid] >= target) hi = mid;
+    if (ld_global(&C[mid]) >= target) hi = mid;
     else lo = mid + 1;
   }
   return lo;
@@ -580,7 +589,7 @@ __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t ste
   if (o.si != sj) return true;
   if (d.hard) return false;
   const W4 t = philox10(step, static_cast<uint32_t>(o.v), kc, SCO_TAG_TH, d.seed, d.chain_id);
-  return unit52(t.x, t.y) < d.theta[m];
+  return unit52(t.x, t.y) < ld_global(&d.theta[m]);
 }
 
 
@@ -673,11 +682,11 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       const int gs = d0.nguide / kSwGuide;
       const int KL = (gs >= 1 && gs * kSwGuide == d0.nguide) ? min(d0.K, kSwC) : 0;
       for (int i = threadIdx.x; i < KL; i += kBlock) {
-        lC[i] = d0.C[i];
-        lhd[i] = d0.hd[i];
+        lC[i] = ld_global(&d0.C[i]);
+        lhd[i] = ld_global(&d0.hd[i]);
       }
       if (KL > 0)
-        for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = d0.guide[b * gs];
+        for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = ld_global(&d0.guide[b * gs]);
       __syncthreads();
       const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs};
       run([&](int) -> const ChainDesc& { return d0; }, tb);
@@ -1275,13 +1284,11 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
             Set taken;
             int rmax = 0;
             bool ready = true;
-            // neighbour j (tile index, -1 for none): same group only; a pending one
-            // counts once decided and one of a higher class must be.  Branch-free, so
-            // the LDS reads of all neighbours are issued together.
-            auto visit = [&](int jn) {
+            // neighbour j (tile index, -1 for none) with word w: same group only; a
+            // pending one counts once decided and one of a higher class must be
+            auto visit_w = [&](int jn, int w) {
               const bool in = jn >= 0 && jn < n;  // outside the tile: another group
               const int jj = in ? jn : i;
-              const int w = cr_ld(jj);
               const int gj = div16(jj, mq);
               const bool pend = (gj >> (p - 1)) & 1;
               const int rj = w >> 8;
@@ -1292,8 +1299,17 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
               rmax = max(rmax, on && pend ? rj : 0);
               taken.add_if(on, cj);
             };
+            auto visit = [&](int jn) { visit_w(jn, cr_ld(jn >= 0 && jn < n ? jn : i)); };
+            // the four lattice neighbours' words are read back to back (the atomic
+            // loads keep their order, so each is issued before any is used)
+            int jt[4], wt[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) visit(nb[u] >= 0 ? nb[u] - v0 : -1);
+            for (int u = 0; u < 4; ++u) {
+              jt[u] = nb[u] >= 0 ? nb[u] - v0 : -1;
+              wt[u] = cr_ld(jt[u] >= 0 && jt[u] < n ? jt[u] : i);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) visit_w(jt[u], wt[u]);
             for (int e = e0; e < e1; ++e) visit(t_adj[e]);
             for (int e = g0; e < g1; ++e) visit(a.col[e] - gt0);
             if (ready) {
@@ -1379,7 +1395,10 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     const long long tot = cpre[nch];
     const long long k0 = tot * blockIdx.x / gridDim.x, k1 = tot * (blockIdx.x + 1) / gridDim.x;
     // the block's list: LDS when its share fits, else its own range of the records
-    int32_t* lst = (k1 - k0 <= kListCap) ? lds_list : reinterpret_cast<int32_t*>(a.rec) + k0;
+    // the block's list: LDS when its share fits, else its own range of the records; the
+    // two cases are separate inlined copies, so LDS accesses stay LDS instructions
+    const bool in_lds = k1 - k0 <= kListCap;
+    int32_t* const lst_mem = reinterpret_cast<int32_t*>(a.rec) + k0;
     // pending index -> chain and chain-local site
     auto site_of = [&](long long k, int& c, int& v) {
       int lo = 0, hi = nch - 1;
@@ -1394,43 +1413,47 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       const uint32_t j = kk / h;
       v = static_cast<int>((2u * j + 1u) * h + (kk - j * h));
     };
-    for (int pass = 0; pass < 2; ++pass) {
-      // kScan sites per thread and iteration, their loads issued together
-      for (long long kb = k0; kb < k1; kb += kScan * kBlock) {
-        int cs[kScan], col[kScan];
-        bool ok[kScan];
+    auto bucket = [&](int32_t* lst) __attribute__((always_inline)) {
+      for (int pass = 0; pass < 2; ++pass) {
+        // kScan sites per thread and iteration, their loads issued together
+        for (long long kb = k0; kb < k1; kb += kScan * kBlock) {
+          int cs[kScan], col[kScan];
+          bool ok[kScan];
 #pragma unroll
-        for (int r = 0; r < kScan; ++r) {
-          const long long k = kb + r * kBlock + tid;
-          ok[r] = k < k1;
-          cs[r] = 0;
-          col[r] = 0;
-          if (ok[r]) {
-            int v;
-            site_of(k, cs[r], v);
-            col[r] = static_cast<int>(a.kw_word[ks.kc[cs[r]].vbase + v] & 0x1FFu);
+          for (int r = 0; r < kScan; ++r) {
+            const long long k = kb + r * kBlock + tid;
+            ok[r] = k < k1;
+            cs[r] = 0;
+            col[r] = 0;
+            if (ok[r]) {
+              int v;
+              site_of(k, cs[r], v);
+              col[r] = static_cast<int>(a.kw_word[ks.kc[cs[r]].vbase + v] & 0x1FFu);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < kScan; ++r) {
+            if (!ok[r]) continue;
+            const int cc = col[r];
+            if (cc >= ks.kc[cs[r]].q) {  // cannot happen after a complete colouring
+              set_flag(a.sync, SCO_FLAG_PALETTE);
+              continue;
+            }
+            if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+            else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(kb + r * kBlock + tid - k0);
           }
         }
-#pragma unroll
-        for (int r = 0; r < kScan; ++r) {
-          if (!ok[r]) continue;
-          const int cc = col[r];
-          if (cc >= ks.kc[cs[r]].q) {  // cannot happen after a complete colouring
-            set_flag(a.sync, SCO_FLAG_PALETTE);
-            continue;
-          }
-          if (pass == 0) atomicAdd(&boff[cc + 1], 1);
-          else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(kb + r * kBlock + tid - k0);
-        }
-      }
-      __syncthreads();
-      if (pass == 0) {
-        if (threadIdx.x == 0)
-          for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-        for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
         __syncthreads();
+        if (pass == 0) {
+          if (threadIdx.x == 0)
+            for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
+          for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
+          __syncthreads();
+        }
       }
-    }
+    };
+    if (in_lds) bucket(lds_list);
+    else bucket(lst_mem);
     mark(a.trace, 200 + p);
     // The classes run without a barrier between them.  A pending site of class cc
     // reads the colours its same-group pending neighbours of higher classes take at
@@ -1442,7 +1465,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     // higher class, which waits on nothing at the top, so by induction over the
     // classes every wait ends (all blocks are resident).
     const int nl = boff[qmax];
-    auto run_level = [&](auto set_tag) {
+    auto run_level = [&](auto set_tag, int32_t* lst) __attribute__((always_inline)) {
       using Set = decltype(set_tag);
       int cls = qmax - 1;  // class of the thread's current position (only decreases)
       for (int jb = 0; jb < nl; jb += kBatchKW * kBlock) {
@@ -1572,8 +1595,9 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
         for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
       }
     };
-    if (qmax <= 64) run_level(ColorSet64{});
-    else run_level(ColorSet{});
+    if (!in_lds) run_level(ColorSet{}, lst_mem);
+    else if (qmax <= 64) run_level(ColorSet64{}, lds_list);
+    else run_level(ColorSet{}, lds_list);
     // the level ends with a full barrier that also publishes the colours
     if (!grid_barrier(a.sync)) return false;
     for (int c = tid; c < nch; c += kBlock)
@@ -1613,7 +1637,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
   const int64_t r1 = min(r0 + S, a.G);
   const int tid = static_cast<int>(threadIdx.x);
-  int32_t* lst = (r1 - r0 <= kListCap) ? lds_list : reinterpret_cast<int32_t*>(a.rec) + r0;
+  int32_t* const lst_mem = reinterpret_cast<int32_t*>(a.rec) + r0;
   // the chains of the block's range are a contiguous run [c_lo, c_hi]
   const int c_lo = r0 < r1 ? a.chunk_chain[r0 >> SCO_CHUNK_SHIFT] : 0;
   const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
@@ -1623,185 +1647,193 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
   for (int c = tid; c < a.n_chains; c += kBlock) bacc[c] = 0;
   __syncthreads();
-  auto desc = [&](int c) -> const ChainDesc& { return local_cd ? lcd[c - c_lo] : a.cd[c]; };
-  // colour buckets of the block's sites: count, offsets, list (kScan sites per thread
-  // and iteration, their loads issued together)
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int64_t gb = r0; gb < r1; gb += kScan * kBlock) {
-      int col[kScan];
-      bool ok[kScan];
+  // The list in LDS and the chain descriptors in LDS (the usual case), or both in
+  // global memory: two inlined copies, so LDS accesses stay LDS instructions.
+  auto body = [&](int32_t* lst, const auto& desc) __attribute__((always_inline)) -> bool {
+    // colour buckets of the block's sites: count, offsets, list (kScan sites per thread
+    // and iteration, their loads issued together)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int64_t gb = r0; gb < r1; gb += kScan * kBlock) {
+        int col[kScan];
+        bool ok[kScan];
 #pragma unroll
-      for (int r = 0; r < kScan; ++r) {
-        const int64_t g = gb + r * kBlock + tid;
-        ok[r] = false;
-        col[r] = 0;
-        if (g < r1) {
-          const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-          const ChainDesc& d = desc(c);
-          ok[r] = static_cast<int>(g - d.vbase) < d.N;
-          if (ok[r]) col[r] = a.color[g];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < kScan; ++r) {
-        if (!ok[r]) continue;
-        const int cc = col[r];
-        if (cc >= qmax) {  // cannot happen after a complete colouring
-          if (pass == 0) set_flag(a.sync, SCO_FLAG_PALETTE);
-          continue;
-        }
-        if (pass == 0) atomicAdd(&boff[cc + 1], 1);
-        else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(gb + r * kBlock + tid - r0);
-      }
-    }
-    __syncthreads();
-    if (pass == 0) {
-      if (threadIdx.x == 0)
-        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
-      __syncthreads();
-    }
-  }
-  mark(a.trace, 22);
-
-  for (int s = 0; s < a.nsw_max; ++s) {
-    for (int cc = 0; cc < qmax; ++cc) {
-      const int k0 = boff[cc], k1 = boff[cc + 1];
-      // every thread of the block runs the same number of iterations; each takes
-      // kBatch sites of the class and loads their neighbour spins before deciding
-      // (sites of one class are not coupled)
-      for (int kb = k0; kb < k1; kb += kBatch * kBlock) {
-        int64_t gs[kBatch];
-        int cs[kBatch], nsum[kBatch], sv[kBatch], q0[kBatch], q1[kBatch];
-        bool live[kBatch];
-#pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
-          const int k = kb + r * kBlock + tid;
-          live[r] = false;
-          gs[r] = 0;
-          cs[r] = 0;
-          nsum[r] = sv[r] = q0[r] = q1[r] = 0;
-          if (k < k1) {
-            gs[r] = r0 + lst[k];
-            cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
-            const ChainDesc& d = desc(cs[r]);
-            const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
-            live[r] = s < nsw;
-            if (live[r]) {
-              const int v = static_cast<int>(gs[r] - d.vbase);
-              const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
-              int nb[4];
-              nn_sites(x, y, d.L, d.periodic, nb);
-#pragma unroll
-              for (int t = 0; t < 4; ++t)
-                if (nb[t] >= 0) nsum[r] += ld_relaxed(&a.spin[d.vbase + nb[t]]);
-              sv[r] = ld_relaxed(&a.spin[gs[r]]);
-              q0[r] = a.row_ptr[gs[r]];
-              q1[r] = a.row_ptr[gs[r] + 1];
-              row_checked(a, q0[r], q1[r]);
-            }
+        for (int r = 0; r < kScan; ++r) {
+          const int64_t g = gb + r * kBlock + tid;
+          ok[r] = false;
+          col[r] = 0;
+          if (g < r1) {
+            const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+            const ChainDesc& d = desc(c);
+            ok[r] = static_cast<int>(g - d.vbase) < d.N;
+            if (ok[r]) col[r] = a.color[g];
           }
         }
-        bool acc[kBatch];
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
-          acc[r] = false;
-          if (!live[r]) continue;
-          const int64_t g = gs[r];
-          const int c = cs[r];
-          const ChainDesc& d = desc(c);
-          const int v = static_cast<int>(g - d.vbase);
-          if (d.hard) {
-            if (q1[r] == q0[r]) {
-              const double pa = d.pacc[sv[r] * nsum[r] + 4];
-              if (pa >= 1.0) {
-                acc[r] = true;
-              } else {
-                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
-                                      d.seed, d.chain_id);
-                acc[r] = unit52(w.x, w.y) < pa;
+        for (int r = 0; r < kScan; ++r) {
+          if (!ok[r]) continue;
+          const int cc = col[r];
+          if (cc >= qmax) {  // cannot happen after a complete colouring
+            if (pass == 0) set_flag(a.sync, SCO_FLAG_PALETTE);
+            continue;
+          }
+          if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+          else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(gb + r * kBlock + tid - r0);
+        }
+      }
+      __syncthreads();
+      if (pass == 0) {
+        if (threadIdx.x == 0)
+          for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
+        for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
+        __syncthreads();
+      }
+    }
+    mark(a.trace, 22);
+
+    for (int s = 0; s < a.nsw_max; ++s) {
+      for (int cc = 0; cc < qmax; ++cc) {
+        const int k0 = boff[cc], k1 = boff[cc + 1];
+        // every thread of the block runs the same number of iterations; each takes
+        // kBatch sites of the class and loads their neighbour spins before deciding
+        // (sites of one class are not coupled)
+        for (int kb = k0; kb < k1; kb += kBatch * kBlock) {
+          int64_t gs[kBatch];
+          int cs[kBatch], nsum[kBatch], sv[kBatch], q0[kBatch], q1[kBatch];
+          bool live[kBatch];
+#pragma unroll
+          for (int r = 0; r < kBatch; ++r) {
+            const int k = kb + r * kBlock + tid;
+            live[r] = false;
+            gs[r] = 0;
+            cs[r] = 0;
+            nsum[r] = sv[r] = q0[r] = q1[r] = 0;
+            if (k < k1) {
+              gs[r] = r0 + lst[k];
+              cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
+              const ChainDesc& d = desc(cs[r]);
+              const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
+              live[r] = s < nsw;
+              if (live[r]) {
+                const int v = static_cast<int>(gs[r] - d.vbase);
+                const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
+                int nb[4];
+                nn_sites(x, y, d.L, d.periodic, nb);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                  if (nb[t] >= 0) nsum[r] += ld_relaxed(&a.spin[d.vbase + nb[t]]);
+                sv[r] = ld_relaxed(&a.spin[gs[r]]);
+                q0[r] = a.row_ptr[gs[r]];
+                q1[r] = a.row_ptr[gs[r] + 1];
+                row_checked(a, q0[r], q1[r]);
               }
             }
-          } else {
-            bool done = false;
-            if (d.precision == 1) {
-              // FP32 local field.  Each term carries the rounding of delta to FP32 and
-              // each addition one more, so |dE32 - dE| <= 2 (n + 1) 2^-24 sum|terms|;
-              // errE takes twice that.  A decision within errE of dE = 0, or with u
-              // within errP of p, is recomputed in FP64 (counted in `rechecks`).
-              float h = d.twoJ32 * static_cast<float>(nsum[r]);
-              float mag = fabsf(h);
-              for (int t = q0[r]; t < q1[r]; ++t) {
-                const float dm = d.delta32[a.attr[t]];
-                h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
-                mag += fabsf(dm);
-              }
-              const float dE = sv[r] > 0 ? h : -h;
-              // a bond-free field 2J nn is exact when 2J is (|nn| <= 4)
-              const float errE = (q1[r] == q0[r] && d.twoJ32_exact)
-                                     ? 0.0f
-                                     : mag * static_cast<float>(q1[r] - q0[r] + 3) * 0x1p-22f;
-              if (dE <= -errE) {
-                acc[r] = done = true;
-              } else if (dE > errE) {
-                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
-                                      d.seed, d.chain_id);
-                const double u = unit52(w.x, w.y);
-                const float x = d.neg_beta32 * dE;
-                const float pr = expf(x);
-                // expf: about one ulp; beta and the product: one rounding each; the
-                // field: errE
-                const double errP =
-                    static_cast<double>(pr) * (static_cast<double>(-d.neg_beta32) * errE * 1.01 + fabs(x) * 0x1p-21 + 0x1p-21) +
-                    0x1p-126;
-                if (fabs(u - static_cast<double>(pr)) > errP) {
-                  acc[r] = u < static_cast<double>(pr);
-                  done = true;
+          }
+          bool acc[kBatch];
+#pragma unroll
+          for (int r = 0; r < kBatch; ++r) {
+            acc[r] = false;
+            if (!live[r]) continue;
+            const int64_t g = gs[r];
+            const int c = cs[r];
+            const ChainDesc& d = desc(c);
+            const int v = static_cast<int>(g - d.vbase);
+            if (d.hard) {
+              if (q1[r] == q0[r]) {
+                const double pa = d.pacc[sv[r] * nsum[r] + 4];
+                if (pa >= 1.0) {
+                  acc[r] = true;
+                } else {
+                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                        d.seed, d.chain_id);
+                  acc[r] = unit52(w.x, w.y) < pa;
                 }
               }
-              if (!done) atomicAdd(&a.st[c].rechecks, 1ull);
-            }
-            if (!done) {
-              double h = d.twoJ * static_cast<double>(nsum[r]);
-              for (int t = q0[r]; t < q1[r]; ++t) {
-                const double dm = d.delta[a.attr[t]];
-                h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+            } else {
+              bool done = false;
+              if (d.precision == 1) {
+                // FP32 local field.  Each term carries the rounding of delta to FP32 and
+                // each addition one more, so |dE32 - dE| <= 2 (n + 1) 2^-24 sum|terms|;
+                // errE takes twice that.  A decision within errE of dE = 0, or with u
+                // within errP of p, is recomputed in FP64 (counted in `rechecks`).
+                float h = d.twoJ32 * static_cast<float>(nsum[r]);
+                float mag = fabsf(h);
+                for (int t = q0[r]; t < q1[r]; ++t) {
+                  const float dm = ld_global(&d.delta32[a.attr[t]]);
+                  h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+                  mag += fabsf(dm);
+                }
+                const float dE = sv[r] > 0 ? h : -h;
+                // a bond-free field 2J nn is exact when 2J is (|nn| <= 4)
+                const float errE = (q1[r] == q0[r] && d.twoJ32_exact)
+                                       ? 0.0f
+                                       : mag * static_cast<float>(q1[r] - q0[r] + 3) * 0x1p-22f;
+                if (dE <= -errE) {
+                  acc[r] = done = true;
+                } else if (dE > errE) {
+                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                        d.seed, d.chain_id);
+                  const double u = unit52(w.x, w.y);
+                  const float x = d.neg_beta32 * dE;
+                  const float pr = expf(x);
+                  // expf: about one ulp; beta and the product: one rounding each; the
+                  // field: errE
+                  const double errP =
+                      static_cast<double>(pr) * (static_cast<double>(-d.neg_beta32) * errE * 1.01 + fabs(x) * 0x1p-21 + 0x1p-21) +
+                      0x1p-126;
+                  if (fabs(u - static_cast<double>(pr)) > errP) {
+                    acc[r] = u < static_cast<double>(pr);
+                    done = true;
+                  }
+                }
+                if (!done) atomicAdd(&a.st[c].rechecks, 1ull);
               }
-              const double dE = sv[r] > 0 ? h : -h;
-              if (dE <= 0.0) {
-                acc[r] = true;
-              } else {
-                const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
-                                      d.seed, d.chain_id);
-                const double u = unit52(w.x, w.y);
-                const double pr = exp(d.neg_beta * dE);
-                if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
-                acc[r] = u < pr;
+              if (!done) {
+                double h = d.twoJ * static_cast<double>(nsum[r]);
+                for (int t = q0[r]; t < q1[r]; ++t) {
+                  const double dm = ld_global(&d.delta[a.attr[t]]);
+                  h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+                }
+                const double dE = sv[r] > 0 ? h : -h;
+                if (dE <= 0.0) {
+                  acc[r] = true;
+                } else {
+                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                                        d.seed, d.chain_id);
+                  const double u = unit52(w.x, w.y);
+                  const double pr = exp(d.neg_beta * dE);
+                  if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
+                  acc[r] = u < pr;
+                }
               }
             }
+            if (acc[r]) st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
           }
-          if (acc[r]) st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
-        }
-        // accepted flips per chain into LDS: one atomic per wave when the wave is one chain
+          // accepted flips per chain into LDS: one atomic per wave when the wave is one chain
 #pragma unroll
-        for (int r = 0; r < kBatch; ++r) {
-          const int c = live[r] ? cs[r] : -1;
-          const int c0 = __shfl(c, 0);
-          if (__ballot(c != c0 && c >= 0) == 0) {
-            const uint64_t mk = __ballot(acc[r]);
-            if (lane_id() == 0 && mk && c0 >= 0) atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(mk)));
-          } else if (acc[r]) {
-            atomicAdd(&bacc[c], 1ull);
+          for (int r = 0; r < kBatch; ++r) {
+            const int c = live[r] ? cs[r] : -1;
+            const int c0 = __shfl(c, 0);
+            if (__ballot(c != c0 && c >= 0) == 0) {
+              const uint64_t mk = __ballot(acc[r]);
+              if (lane_id() == 0 && mk && c0 >= 0) atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(mk)));
+            } else if (acc[r]) {
+              atomicAdd(&bacc[c], 1ull);
+            }
           }
         }
+        // between the classes only the spins change (coherent accesses); the phase ends
+        // with a full barrier
+        const bool last = s + 1 == a.nsw_max && cc + 1 == qmax;
+        if (!(last ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
+        mark(a.trace, 1000 + cc);
       }
-      // between the classes only the spins change (coherent accesses); the phase ends
-      // with a full barrier
-      const bool last = s + 1 == a.nsw_max && cc + 1 == qmax;
-      if (!(last ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
-      mark(a.trace, 1000 + cc);
     }
-  }
+    return true;
+  };
+  const bool ok = (local_cd && r1 - r0 <= kListCap)
+                      ? body(lds_list, [&](int c) -> const ChainDesc& { return lcd[c - c_lo]; })
+                      : body(lst_mem, [&](int c) -> const ChainDesc& { return a.cd[c]; });
+  if (!ok) return false;
   for (int c = tid; c < a.n_chains; c += kBlock)
     if (bacc[c]) atomicAdd(&a.st[c].accepted, bacc[c]);
   if (blockIdx.x == 0)
