@@ -1662,7 +1662,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
           ok[r] = false;
           col[r] = 0;
           if (g < r1) {
-            const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+            const int c = c_lo == c_hi ? c_lo : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
             const ChainDesc& d = desc(c);
             ok[r] = static_cast<int>(g - d.vbase) < d.N;
             if (ok[r]) col[r] = a.color[g];
@@ -1709,7 +1709,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
             nsum[r] = sv[r] = q0[r] = q1[r] = 0;
             if (k < k1) {
               gs[r] = r0 + lst[k];
-              cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
+              cs[r] = c_lo == c_hi ? c_lo : a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
               const ChainDesc& d = desc(cs[r]);
               const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
               live[r] = s < nsw;

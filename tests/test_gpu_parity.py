@@ -54,6 +54,20 @@ def test_medium_periodic_three_temperatures(kappa):
     log(f"  tolerated near ties: {out['tolerated']}")
 
 
+@pytest.mark.parametrize("kappa", [1.0, 2.0])
+def test_several_sweeps_after_device_wide_levels(kappa):
+    """L=640 periodic (N = 410k: KW levels above the LDS tile run device-wide), four
+    sweeps per step: every sweep's neighbour order comes from the final colours, and a
+    sweep may start before the previous one has ended elsewhere on the lattice."""
+    params = [workloads.chain(640, True, 1.1, kappa, chain_id=0, n_sw=4)]
+    log(f"640 periodic, n_sw=4, kappa={kappa}")
+    out = run_parity(params, 3, graph_every=1, obs_every=2)
+    go = out["gpu"].observables()[0]
+    # levels above P = floor(log2(28672 / q)) (the largest LDS tile) ran device-wide
+    assert go["kw_levels"] > int(np.floor(np.log2(28672 / go["q"])))
+    log(f"  tolerated near ties: {out['tolerated']}")
+
+
 def test_ragged_batch_of_chains():
     """Chains of different L, boundaries, kappa and n_sw in one launch."""
     params = [workloads.chain(8, True, 2.0, 2.0, chain_id=0, n_sw=2),
