@@ -126,7 +126,7 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_rec = take(sizeof(int4) * G);
   lay.off_ecount = take(sizeof(uint32_t) * lay.nchunks);
   lay.off_trace = take(sizeof(unsigned long long) * SCO_TRACE_SLOTS);
-  lay.ntiles = G / (16 * SCO_CHUNK) + 2;  // tiles of the degree scan
+  lay.ntiles = G / (SCO_SCAN_ITEMS * SCO_CHUNK) + 2;  // tiles of the degree scan
   lay.off_agg = take(sizeof(long long) * lay.ntiles);
   lay.off_spin_bak = take(G);  // autotuning trials restore the chain from here
   lay.off_st_bak = take(sizeof(ChainState) * n);

@@ -16,6 +16,7 @@
 #define SCO_MAXLEVEL 32         // KW levels are at most ceil(log2(N)) <= 31
 #define SCO_MAXCHAINS 256
 #define SCO_TILE_MAX 28672      // sites of a KW tile held in LDS (local levels): 7 * 2^12
+#define SCO_SCAN_ITEMS 21       // values per thread of a degree-scan tile (21504-value tiles)
 #define SCO_GUIDE_BITS 14       // guide table of the cumulative couplings: 2^14 buckets
 #define SCO_BAR_GROUPS 32       // first-level arrival groups of the grid barrier
 

@@ -714,7 +714,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
 // before each of its tiles and scans the tile.  Global memory is read and written in
 // coalesced rows (item k * kBlock + thread); the scan order goes through LDS, padded
 // one word in 32 against bank conflicts.  out[n] = total.  out may alias in.
-constexpr int kItems = 16;
+constexpr int kItems = SCO_SCAN_ITEMS;  // one tile per block at L = 2304 on 256 blocks
 constexpr int kTile = kBlock * kItems;
 constexpr int kScanLds = kTile + kTile / 32;  // words of the padded tile in LDS
 
@@ -726,10 +726,11 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, in
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   const int tid = static_cast<int>(threadIdx.x);
-  // padded LDS addresses (one word in 32): row item k of this thread at
-  // rowb + k kRow, scan item i at colb + i
-  const int rowb = tid + (tid >> 5), colb = tid * kItems + (tid >> 1);
+  // padded LDS addresses (one word in 32: index x at x + x / 32): row item k of this
+  // thread at rowb + k kRow, scan item i at pad(cb + i)
+  const int rowb = tid + (tid >> 5), cb = tid * kItems;
   constexpr int kRow = kBlock + kBlock / 32;
+  auto pad = [](int x) { return x + (x >> 5); };
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const int tb = t * kTile + tid;
     long long s = 0;
@@ -756,7 +757,7 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, in
     pre = block_sum(pre);  // in every thread; its barriers also order the LDS stores
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) s += lds[colb + i];
+    for (int i = 0; i < kItems; ++i) s += lds[pad(cb + i)];
     int32_t incl = s;
     for (int o = 1; o < 64; o <<= 1) {
       const int32_t x = __shfl_up(incl, o);
@@ -769,8 +770,8 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, in
     int32_t run = static_cast<int32_t>(pre) + woff + incl - s;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-      const int32_t v = lds[colb + i];
-      lds[colb + i] = run;
+      const int32_t v = lds[pad(cb + i)];
+      lds[pad(cb + i)] = run;
       run += v;
     }
     if (t == nt - 1 && threadIdx.x == kBlock - 1) out[n] = run;
