@@ -144,8 +144,9 @@ int sco_phase_times(sco_ctx* ctx, float* out3);
  * (an id and the wall clock) at each phase boundary of every launch.  sco_trace_read
  * returns the marks of the last launch (ids, microseconds since its first mark) and
  * their count in *n; it synchronises.  Ids: 1-6 switching (draws, scan, scatter,
- * row sort), 10-13 colouring (30 bonds of block 0's first tile staged, 40+p its
- * tile level p done, 200+p global level p bucketed, 100+p global level p done),
+ * row sort), 10-13 colouring (30 bonds of block 0's first tile staged, 60+p and
+ * 80+p its tile level p counted and bucketed, 40+p that level done, 200+p global
+ * level p bucketed, 100+p global level p done),
  * 20-22 sweeps (1000+k colour class k).  Diagnostic only; costs a small copy per
  * launch. */
 int sco_trace(sco_ctx* ctx, int enable);

@@ -32,6 +32,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kBatch = 3;
 constexpr int kBatchKW = 1;  // in the KW classes
 constexpr int kScan = 4;
+constexpr int kOwners = 2;  // owners in flight per thread in the switching
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of multiply/xor with the Weyl key
@@ -434,33 +435,54 @@ struct Owner {
   bool live;
 };
 
-// Starts the next owner site of this thread in chunks [next, ch1); false when none
-// is left.
-// desc_of(c) gives chain c's descriptor (with a block-uniform chain, from scalar loads).
+// Deals the next owner sites of the block's chunks [ch0, ch1) to the lanes that ask
+// (need): one LDS atomic per wave and round, lanes in order; a lane whose site is
+// chunk padding asks again.  A lane that finds the pool empty gets a dead owner and
+// clears `pool`.  Every lane of the wave must call it.  c_uni >= 0: every chunk of
+// the range belongs to chain c_uni.  Dealing owners from one pool keeps the lanes of
+// a wave (and the waves of a block) busy until the block's sites run out, instead of
+// each lane working through a fixed share whose draw count varies.
 template <class Desc>
-__device__ __forceinline__ bool owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, int& next, int ch1) {
-  while (next < ch1) {
-    const int64_t g = (static_cast<int64_t>(next) << SCO_CHUNK_SHIFT) + threadIdx.x;
-    const int c = a.chunk_chain[next];
-    ++next;
-    const ChainDesc& d = desc_of(c);
-    const int v = static_cast<int>(g - d.vbase);
-    if (v >= d.N) continue;  // chunk padding
-    o.g = g;
-    o.v = v;
-    o.c = c;
-    o.y = idiv_fp(v, d.inv_L);
-    o.x = v - o.y * d.L;
-    o.pos = -1;
-    o.k = 0;
-    o.Cpos = 0.0;
-    o.si = a.spin[g];
-    o.ns = 0;
-    o.live = true;
-    return true;
+__device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, bool need, bool& pool,
+                                           uint32_t* s_next, int ch0, int ch1, int c_uni) {
+  const uint32_t lane = lane_id();
+  const uint32_t total = static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT;
+  bool want = need;
+  while (true) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) break;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    uint32_t base = 0;
+    if (static_cast<int>(lane) == leader) base = atomicAdd(s_next, static_cast<uint32_t>(__popcll(m)));
+    base = __shfl(base, leader);
+    if (want) {
+      const uint32_t idx = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+      if (idx >= total) {
+        o.live = false;
+        pool = false;
+        want = false;
+      } else {
+        const int64_t g = (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT) + idx;
+        const int c = c_uni >= 0 ? c_uni : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+        const ChainDesc& d = desc_of(c);
+        const int v = static_cast<int>(g - d.vbase);
+        if (v < d.N) {  // else chunk padding: ask again
+          o.g = g;
+          o.v = v;
+          o.c = c;
+          o.y = idiv_fp(v, d.inv_L);
+          o.x = v - o.y * d.L;
+          o.pos = -1;
+          o.k = 0;
+          o.Cpos = 0.0;
+          o.si = a.spin[g];
+          o.ns = 0;
+          o.live = true;
+          want = false;
+        }
+      }
+    }
   }
-  o.live = false;
-  return false;
 }
 
 // The first kSwC entries of a chain's cumulative couplings C and displacements hd,
@@ -602,21 +624,21 @@ __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t ste
 // Philox(step, v, k>>1, SW); the thinning draw of candidate k is Philox(step, v, k, TH).
 //
 // Block b owns a contiguous range of chunks; each thread keeps two owners of that
-// range in flight and starts the next one as soon as one ends, so a wave is not held
-// by its slowest owner.  Survivors go to the block's region (one LDS atomic per wave
+// range in flight and takes the next from the block's pool as soon as one ends, so a
+// wave is held neither by its slowest owner nor by its busiest lane.  Survivors go to the block's region (one LDS atomic per wave
 // and append); its count is written to the entry of the range's first chunk.
 __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, int32_t* lds_raw) {
-  __shared__ uint32_t s_count;
+  __shared__ uint32_t s_count, s_next;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
   const uint32_t e_base = static_cast<uint32_t>(ch0) * cap_chunk;
   const uint32_t cap_blk = static_cast<uint32_t>(ch1 - ch0) * cap_chunk;
-  if (threadIdx.x == 0) s_count = 0;
+  if (threadIdx.x == 0) s_count = s_next = 0;
   __syncthreads();
   const uint32_t lane = lane_id();
   // returns the owner's count of stored survivors after this append
-  auto append = [&](bool f, int64_t g, int c, int j, int m, int ns) -> int {
+  auto append = [&](bool f, int64_t g, int v, int j, int m, int ns) -> int {
     const uint64_t mask = __ballot(f);
     if (mask == 0) return ns;
     const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
@@ -627,7 +649,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       const uint32_t eo = e0 + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
       if (eo < cap_blk) {
         const uint32_t e = e_base + eo;
-        const int32_t gj = static_cast<int32_t>(a.cd[c].vbase + j);
+        const int32_t gj = static_cast<int32_t>(g - v + j);  // the chain's base is g - v
         a.ea[e] = static_cast<int32_t>(g);
         a.eb[e] = gj;
         a.em[e] = m;
@@ -638,34 +660,49 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     }
     return ns;
   };
-  auto run = [&](const auto& desc_of, const SwitchTables& tb) {
-    int next = ch0;
-    Owner A, B;
-    A.ns = B.ns = 0;
-    owner_take(a, desc_of, A, next, ch1);
-    owner_take(a, desc_of, B, next, ch1);
-    while (__ballot(A.live || B.live) != 0) {
-      // both candidates first, then both partner spins in flight together
-      int jA = -1, mA = 0, jB = -1, mB = 0;
-      uint32_t kA = 0, kB = 0;
-      const bool cA = A.live && owner_candidate(a, desc_of, tb, step, A, jA, mA, kA);
-      const bool cB = B.live && owner_candidate(a, desc_of, tb, step, B, jB, mB, kB);
-      const int sA = cA && jA >= 0 ? a.spin[desc_of(A.c).vbase + jA] : 0;
-      const int sB = cB && jB >= 0 ? a.spin[desc_of(B.c).vbase + jB] : 0;
-      const bool fA = cA && owner_survives(desc_of, step, A, jA, mA, kA, sA);
-      const bool fB = cB && owner_survives(desc_of, step, B, jB, mB, kB, sB);
-      A.ns = append(fA, A.g, A.c, jA, mA, A.ns);
-      B.ns = append(fB, B.g, B.c, jB, mB, B.ns);
-      // an ended owner's survivor count starts its row's cursor for the partners
-      if (!A.live) {
-        if (A.ns) a.fill[A.g] = A.ns;
-        A.ns = 0;
-        owner_take(a, desc_of, A, next, ch1);
+  auto run = [&](const auto& desc_of, const SwitchTables& tb, int c_uni) {
+    bool pool = true;
+    Owner O[kOwners];
+#pragma unroll
+    for (int u = 0; u < kOwners; ++u) {
+      O[u].ns = 0;
+      O[u].live = false;
+      owner_take(a, desc_of, O[u], pool, pool, &s_next, ch0, ch1, c_uni);
+    }
+    auto any_live = [&]() {
+      bool l = false;
+#pragma unroll
+      for (int u = 0; u < kOwners; ++u) l = l || O[u].live;
+      return l;
+    };
+    while (__ballot(any_live()) != 0) {
+      // every owner's candidate first, then all partner spins in flight together
+      int jc[kOwners], mc[kOwners], sc[kOwners];
+      uint32_t kc[kOwners];
+      bool cc[kOwners];
+#pragma unroll
+      for (int u = 0; u < kOwners; ++u) {
+        jc[u] = -1;
+        mc[u] = 0;
+        kc[u] = 0;
+        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u]);
       }
-      if (!B.live) {
-        if (B.ns) a.fill[B.g] = B.ns;
-        B.ns = 0;
-        owner_take(a, desc_of, B, next, ch1);
+#pragma unroll
+      for (int u = 0; u < kOwners; ++u)
+        sc[u] = cc[u] && jc[u] >= 0 ? a.spin[desc_of(O[u].c).vbase + jc[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kOwners; ++u) {
+        const bool f = cc[u] && owner_survives(desc_of, step, O[u], jc[u], mc[u], kc[u], sc[u]);
+        O[u].ns = append(f, O[u].g, O[u].v, jc[u], mc[u], O[u].ns);
+      }
+      // an ended owner's survivor count starts its row's cursor for the partners
+#pragma unroll
+      for (int u = 0; u < kOwners; ++u) {
+        if (!O[u].live && O[u].ns) {
+          a.fill[O[u].g] = O[u].ns;
+          O[u].ns = 0;
+        }
+        owner_take(a, desc_of, O[u], !O[u].live && pool, pool, &s_next, ch0, ch1, c_uni);
       }
     }
   };
@@ -689,10 +726,10 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = ld_global(&d0.guide[b * gs]);
       __syncthreads();
       const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs};
-      run([&](int) -> const ChainDesc& { return d0; }, tb);
+      run([&](int) -> const ChainDesc& { return d0; }, tb, c_lo);
     } else {
       const SwitchTables tb{nullptr, nullptr, nullptr, 0, 0.0};
-      run([&](int c) -> const ChainDesc& { return a.cd[c]; }, tb);
+      run([&](int c) -> const ChainDesc& { return a.cd[c]; }, tb, -1);
     }
   }
   __syncthreads();
