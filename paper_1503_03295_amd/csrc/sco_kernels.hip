@@ -30,7 +30,6 @@ constexpr int kWaves = kBlock / 64;
 // Items per thread whose loads are issued together: in colour classes (kBatch) and in
 // scans over sites or survivors (kScan).
 constexpr int kBatch = 3;
-constexpr int kBatchKW = 1;  // in the KW classes
 constexpr int kScan = 4;
 constexpr int kOwners = 2;  // owners in flight per thread in the switching
 
@@ -1401,6 +1400,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
   __shared__ int32_t brounds[SCO_MAXCHAINS];
   __shared__ long long cpre[SCO_MAXCHAINS + 1];
   __shared__ long long wtot[kWaves];
+  __shared__ int32_t s_pos;  // next list position to deal at the current level
   const uint32_t lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int tid = static_cast<int>(threadIdx.x);
@@ -1428,6 +1428,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       if (c == nch - 1) cpre[nch] = off + incl;
       for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
       for (int k = tid; k < nch; k += kBlock) brounds[k] = 0;
+      if (tid == 0) s_pos = 0;
       __syncthreads();
     }
     const long long tot = cpre[nch];
@@ -1497,112 +1498,103 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     // reads the colours its same-group pending neighbours of higher classes take at
     // this level and ignores the lower ones (those wait for it), so it decides as soon
     // as every such word carries this level, and the decision does not depend on when
-    // the words arrived.  Each thread takes the block's list from the top class down,
-    // in increasing position, and a batch of a thread keeps deciding whichever of its
-    // sites are ready and re-reading the words of the others: every wait is on a
-    // higher class, which waits on nothing at the top, so by induction over the
-    // classes every wait ends (all blocks are resident).
+    // the words arrived.  List positions (top class first) are dealt to the lanes from
+    // a block-wide counter, so each lane's positions increase; a lane holds one site
+    // at a time, re-reads its words while it waits, and takes the next position once
+    // it has decided, so a waiting lane holds up neither its wave nor its block.
+    // Every wait is on a higher class: the highest undecided class is always ready
+    // wherever it is held, and an untaken site of it can only be behind held sites of
+    // that same class, so by induction every wait ends (all blocks are resident).
     const int nl = boff[qmax];
     auto run_level = [&](auto set_tag, int32_t* lst) __attribute__((always_inline)) {
       using Set = decltype(set_tag);
-      int cls = qmax - 1;  // class of the thread's current position (only decreases)
-      for (int jb = 0; jb < nl; jb += kBatchKW * kBlock) {
-        int gs[kBatchKW], cs[kBatchKW], cl[kBatchKW], rb[kBatchKW], re[kBatchKW];
-        int nbs[kBatchKW][4];
-        uint32_t wn[kBatchKW][4];
-        bool pend[kBatchKW];
+      const uint32_t lane = lane_id();
+      int cls = qmax - 1;  // class of the lane's current position (only decreases)
+      bool have = false, more = true;
+      int kx = 0, cl = 0, c = 0, rb = 0, re = 0, pb = -1;
+      int32_t g = 0;
+      int nbs[4] = {-1, -1, -1, -1};
+      uint32_t wn[4] = {0u, 0u, 0u, 0u}, wb = 0u;
+      int cloc = -1, rloc = 0;
+      for (uint32_t spin = 0;; ++spin) {
+        // lanes without a site take the next positions: one LDS atomic per wave
+        const bool need = !have && more;
+        const uint64_t nm = __ballot(need);
+        bool fresh = false;
+        if (nm != 0) {
+          const int leader = __ffsll(static_cast<unsigned long long>(nm)) - 1;
+          int base = 0;
+          if (static_cast<int>(lane) == leader) base = atomicAdd(&s_pos, __popcll(nm));
+          base = __shfl(base, leader);
+          if (need) {
+            const int j = base + __popcll(nm & ((1ull << lane) - 1ull));
+            if (j >= nl) {
+              more = false;
+            } else {
+              kx = nl - 1 - j;
+              while (kx < boff[cls]) --cls;
+              cl = cls;
+              int v;
+              site_of(k0 + lst[kx], c, v);
+              const KwChain& K = ks.kc[c];
+              const int32_t vb = static_cast<int32_t>(K.vbase);
+              g = vb + v;
+              const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
+              nn_sites(x, y, K.L, K.periodic, nbs);
 #pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          const int j = jb + r * kBlock + tid;
-          pend[r] = j < nl;
-          gs[r] = 0;
-          cs[r] = 0;
-          cl[r] = 0;
-          rb[r] = re[r] = 0;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            nbs[r][t] = -1;
-            wn[r][t] = 0;
+              for (int t = 0; t < 4; ++t) wn[t] = nbs[t] >= 0 ? ld_relaxed(&a.kw_word[vb + nbs[t]]) : 0u;
+              rb = a.row_ptr[g];
+              re = a.row_ptr[g + 1];
+              row_checked(a, rb, re);
+              pb = re > rb ? a.col[rb] - vb : -1;
+              wb = pb >= 0 ? ld_relaxed(&a.kw_word[vb + pb]) : 0u;
+              have = true;
+              fresh = true;
+            }
           }
-          if (pend[r]) {
-            const int kx = nl - 1 - j;
-            while (kx < boff[cls]) --cls;
-            cl[r] = cls;
-            int v;
-            site_of(k0 + lst[kx], cs[r], v);
-            const KwChain& K = ks.kc[cs[r]];
-            const int32_t vb = static_cast<int32_t>(K.vbase);
-            gs[r] = vb + v;
-            const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
-            nn_sites(x, y, K.L, K.periodic, nbs[r]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (nbs[r][t] >= 0) wn[r][t] = ld_relaxed(&a.kw_word[vb + nbs[r][t]]);
-            rb[r] = a.row_ptr[gs[r]];
-            re[r] = a.row_ptr[gs[r] + 1];
-            row_checked(a, rb[r], re[r]);
-          }
         }
-        // the first bond partner and its word
-        int pb[kBatchKW];
-        uint32_t wb[kBatchKW];
+        if (__ballot(have || more) == 0) break;
+        if (have && !fresh) {
+          // still waiting: re-read the words where every XCD sees one value
+          const int32_t vb = static_cast<int32_t>(ks.kc[c].vbase);
 #pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-          pb[r] = re[r] > rb[r] ? a.col[rb[r]] - vb : -1;
+          for (int t = 0; t < 4; ++t)
+            if (nbs[t] >= 0) wn[t] = ld_poll(&a.kw_word[vb + nbs[t]]);
+          if (pb >= 0) wb = ld_poll(&a.kw_word[vb + pb]);
         }
-#pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-          wb[r] = pb[r] >= 0 ? ld_relaxed(&a.kw_word[vb + pb[r]]) : 0u;
-        }
-        int cdone[kBatchKW], rdone[kBatchKW];
-#pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) {
-          cdone[r] = -1;
-          rdone[r] = 0;
-        }
-        for (uint32_t spin = 0;; ++spin) {
-          bool waiting = false;
-#pragma unroll
-          for (int r = 0; r < kBatchKW; ++r) {
-            if (!pend[r]) continue;
-            const int32_t g = gs[r];
-            const int c = cs[r];
-            const KwChain& K = ks.kc[c];
-            const int q = K.q;
-            const int32_t vb = static_cast<int32_t>(K.vbase);
-            const int grp = idiv_fp(g - vb, K.inv_q) >> p;
-            Set taken;
-            int rmax = 0;
-            bool ready = true;
-            // neighbour u (chain-local) with word w: same group only; a pending one
-            // counts once decided at this level, and one of a higher class must be
-            auto visit = [&](int u, uint32_t w) {
-              const int gu = idiv_fp(u, K.inv_q);
-              if ((gu >> p) != grp) return;  // another group at this level
-              if ((gu >> (p - 1)) & 1) {     // pending at this level
-                if (static_cast<int>((w >> 18) & 0x1Fu) != p) {
-                  const int cu = static_cast<int>(w & 0x1FFu);
-                  if (cu > cl[r] && cu < q) ready = false;  // not yet decided
-                  return;  // a lower class: decides after this site
-                }
-                rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
+        bool waiting = false;
+        if (have) {
+          const KwChain& K = ks.kc[c];
+          const int q = K.q;
+          const int32_t vb = static_cast<int32_t>(K.vbase);
+          const int grp = idiv_fp(g - vb, K.inv_q) >> p;
+          Set taken;
+          int rmax = 0;
+          bool ready = true;
+          // neighbour u (chain-local) with word w: same group only; a pending one
+          // counts once decided at this level, and one of a higher class must be
+          auto visit = [&](int u, uint32_t w) {
+            const int gu = idiv_fp(u, K.inv_q);
+            if ((gu >> p) != grp) return;  // another group at this level
+            if ((gu >> (p - 1)) & 1) {     // pending at this level
+              if (static_cast<int>((w >> 18) & 0x1Fu) != p) {
+                const int cu = static_cast<int>(w & 0x1FFu);
+                if (cu > cl && cu < q) ready = false;  // not yet decided
+                return;  // a lower class: decides after this site
               }
-              taken.add(static_cast<int>(w & 0x1FFu));
-            };
+              rmax = max(rmax, static_cast<int>((w >> 9) & 0x1FFu));
+            }
+            taken.add(static_cast<int>(w & 0x1FFu));
+          };
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (nbs[r][t] >= 0) visit(nbs[r][t], wn[r][t]);
-            if (pb[r] >= 0) visit(pb[r], wb[r]);
-            for (int e = rb[r] + 1; e < re[r]; ++e) {
-              const int u = a.col[e] - vb;
-              visit(u, spin == 0 ? ld_relaxed(&a.kw_word[vb + u]) : ld_poll(&a.kw_word[vb + u]));
-            }
-            if (!ready) {
-              waiting = true;
-              continue;
-            }
+          for (int t = 0; t < 4; ++t)
+            if (nbs[t] >= 0) visit(nbs[t], wn[t]);
+          if (pb >= 0) visit(pb, wb);
+          for (int e = rb + 1; e < re; ++e) {
+            const int u = a.col[e] - vb;
+            visit(u, fresh ? ld_relaxed(&a.kw_word[vb + u]) : ld_poll(&a.kw_word[vb + u]));
+          }
+          if (ready) {
             int nc = taken.first_free();
             if (nc >= q) {
               set_flag(a.sync, SCO_FLAG_PALETTE);
@@ -1610,28 +1602,25 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
             }
             st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
                                           static_cast<uint32_t>(nc));
-            cdone[r] = c;
-            rdone[r] = rmax + 1;
-            pend[r] = false;
+            if (c != cloc) {
+              if (cloc >= 0) atomicMax(&brounds[cloc], rloc);
+              cloc = c;
+              rloc = 0;
+            }
+            rloc = max(rloc, rmax + 1);
+            have = false;
+          } else {
+            waiting = true;
           }
-          if (!waiting) break;
+        }
+        // pause only when no lane of the wave took new work
+        if (__ballot(waiting) != 0 && nm == 0) {
           if (spin > kSpinLimit) set_flag(a.sync, SCO_FLAG_TIMEOUT);
           if ((spin & 255u) == 255u && timed_out(a.sync)) break;
           __builtin_amdgcn_s_sleep(1);
-          // re-read the words of the sites still waiting where every XCD sees one value
-#pragma unroll
-          for (int r = 0; r < kBatchKW; ++r) {
-            if (!pend[r]) continue;
-            const int32_t vb = static_cast<int32_t>(ks.kc[cs[r]].vbase);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (nbs[r][t] >= 0) wn[r][t] = ld_poll(&a.kw_word[vb + nbs[r][t]]);
-            if (pb[r] >= 0) wb[r] = ld_poll(&a.kw_word[vb + pb[r]]);
-          }
         }
-#pragma unroll
-        for (int r = 0; r < kBatchKW; ++r) wave_max_to(brounds, cdone[r], rdone[r]);
       }
+      wave_max_to(brounds, cloc, rloc);
     };
     if (!in_lds) run_level(ColorSet{}, lst_mem);
     else if (qmax <= 64) run_level(ColorSet64{}, lds_list);
