@@ -1125,7 +1125,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
   __shared__ int32_t t_off[SCO_MAXQ + 1];
   __shared__ int32_t t_fill[SCO_MAXQ];
   __shared__ int32_t t_wsum[kWaves];
-  __shared__ int32_t t_rounds, t_nbonded;
+  __shared__ int32_t t_rounds, t_nbonded, t_pos;
   const uint32_t lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int tid = static_cast<int>(threadIdx.x);
@@ -1242,7 +1242,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       const uint32_t mH = magic16(static_cast<uint32_t>(H));
       const int npend = static_cast<int>(pending_count(n, H));
       for (int k = threadIdx.x; k <= q; k += kBlock) t_off[k] = 0;
-      if (threadIdx.x == 0) t_rounds = 0;
+      if (threadIdx.x == 0) t_rounds = t_pos = 0;
       __syncthreads();
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
@@ -1285,39 +1285,67 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       // The classes run from the top down with no barrier between them: a site
       // decides as soon as its same-group pending neighbours of higher classes have
       // (their LDS words carry a round), re-reading the words while it waits; lower
-      // classes are ignored and wait for it.  Each thread takes the list from the top
-      // class down in increasing position, so every wait is on an earlier position of
-      // a higher class and, by induction over the classes, ends.
+      // classes are ignored and wait for it.  List positions are dealt to the lanes
+      // from a block counter in increasing order (top class first); a lane holds one
+      // site at a time, so a waiting lane holds up neither its wave nor the block, and
+      // every wait is on an earlier position of a higher class and, by induction over
+      // the classes, ends.
       auto run_classes = [&](auto set_tag) {
         using Set = decltype(set_tag);
         // the words are read and written with workgroup-scope atomics: every wait sees
         // the other waves' decisions, and the accesses stay LDS instructions
         auto cr_ld = [&](int k) -> int { return __hip_atomic_load(&t_cr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
         int tmax = 0;
-        int cls = q - 1;  // class of the thread's current position (only decreases)
-        for (int j = tid; j < npend; j += kBlock) {
-          const int kx = npend - 1 - j;
-          while (kx < t_off[cls]) --cls;
-          const int i = t_list[kx];
-          const int grp = div16(i, mq) >> p;
-          const int t = x0 + i, dy = div16(t, mL);
-          int nb[4];
-          nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
-          int e0 = 0, e1 = 0, g0 = 0, g1 = 0;  // in-tile bonds in LDS, or the row in memory
-          const uint32_t mw = t_bmask[i >> 5];
-          if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
-            const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
-            const int eb = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
-            if (eb <= kAdjCap) {
-              e0 = t_boff[r];
-              e1 = eb;
-            } else {
-              g0 = a.row_ptr[gt0 + i];
-              g1 = a.row_ptr[gt0 + i + 1];
-              row_checked(a, g0, g1);
+        int cls = q - 1;  // class of the lane's current position (only decreases)
+        bool have = false, more = true;
+        int i = 0, cl = 0, grp = 0;
+        int jt[4] = {-1, -1, -1, -1};
+        int e0 = 0, e1 = 0, g0 = 0, g1 = 0;  // in-tile bonds in LDS, or the row in memory
+        for (uint32_t spin = 0;; ++spin) {
+          // lanes without a site take the next positions: one LDS atomic per wave
+          const bool need = !have && more;
+          const uint64_t nm = __ballot(need);
+          if (nm != 0) {
+            const int leader = __ffsll(static_cast<unsigned long long>(nm)) - 1;
+            int base = 0;
+            if (static_cast<int>(lane) == leader) base = atomicAdd(&t_pos, __popcll(nm));
+            base = __shfl(base, leader);
+            if (need) {
+              const int j = base + __popcll(nm & ((1ull << lane) - 1ull));
+              if (j >= npend) {
+                more = false;
+              } else {
+                const int kx = npend - 1 - j;
+                while (kx < t_off[cls]) --cls;
+                cl = cls;
+                i = t_list[kx];
+                grp = div16(i, mq) >> p;
+                const int t = x0 + i, dy = div16(t, mL);
+                int nb[4];
+                nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) jt[u] = nb[u] >= 0 ? nb[u] - v0 : -1;
+                e0 = e1 = g0 = g1 = 0;
+                const uint32_t mw = t_bmask[i >> 5];
+                if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
+                  const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
+                  const int eb = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
+                  if (eb <= kAdjCap) {
+                    e0 = t_boff[r];
+                    e1 = eb;
+                  } else {
+                    g0 = a.row_ptr[gt0 + i];
+                    g1 = a.row_ptr[gt0 + i + 1];
+                    row_checked(a, g0, g1);
+                  }
+                }
+                have = true;
+              }
             }
           }
-          for (uint32_t spin = 0;; ++spin) {
+          if (__ballot(have || more) == 0) break;
+          bool waiting = false;
+          if (have) {
             Set taken;
             int rmax = 0;
             bool ready = true;
@@ -1332,19 +1360,16 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
               const bool same = in && (gj >> p) == grp;
               const bool on = same && (!pend || rj != 0);
               const int cj = w & 0xFF;
-              ready = ready && !(same && pend && rj == 0 && cj > cls && cj < q);
+              ready = ready && !(same && pend && rj == 0 && cj > cl && cj < q);
               rmax = max(rmax, on && pend ? rj : 0);
               taken.add_if(on, cj);
             };
             auto visit = [&](int jn) { visit_w(jn, cr_ld(jn >= 0 && jn < n ? jn : i)); };
             // the four lattice neighbours' words are read back to back (the atomic
             // loads keep their order, so each is issued before any is used)
-            int jt[4], wt[4];
+            int wt[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              jt[u] = nb[u] >= 0 ? nb[u] - v0 : -1;
-              wt[u] = cr_ld(jt[u] >= 0 && jt[u] < n ? jt[u] : i);
-            }
+            for (int u = 0; u < 4; ++u) wt[u] = cr_ld(jt[u] >= 0 && jt[u] < n ? jt[u] : i);
 #pragma unroll
             for (int u = 0; u < 4; ++u) visit_w(jt[u], wt[u]);
             for (int e = e0; e < e1; ++e) visit(t_adj[e]);
@@ -1358,8 +1383,13 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
               __hip_atomic_store(&t_cr[i], static_cast<uint16_t>(nc | ((rmax + 1) << 8)), __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
               tmax = max(tmax, rmax + 1);
-              break;
+              have = false;
+            } else {
+              waiting = true;
             }
+          }
+          // pause only when no lane of the wave took new work
+          if (__ballot(waiting) != 0 && nm == 0) {
             if (spin > kSpinLimit) {
               set_flag(a.sync, SCO_FLAG_TIMEOUT);
               break;
@@ -1449,7 +1479,8 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       c = lo;
       const uint32_t kk = static_cast<uint32_t>(k - cpre[c]);
       const uint32_t h = static_cast<uint32_t>(ks.kc[c].q) << (p - 1);
-      const uint32_t j = kk / h;
+      // kk / h = (kk / 2^(p-1)) / q, exact through the double reciprocal of q
+      const uint32_t j = static_cast<uint32_t>(idiv_fp(static_cast<int>(kk >> (p - 1)), ks.kc[c].inv_q));
       v = static_cast<int>((2u * j + 1u) * h + (kk - j * h));
     };
     auto bucket = [&](int32_t* lst) __attribute__((always_inline)) {
