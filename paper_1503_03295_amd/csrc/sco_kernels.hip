@@ -32,6 +32,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kBatch = 3;
 constexpr int kScan = 4;
 constexpr int kOwners = 2;  // owners in flight per thread in the switching
+constexpr int kStage = 8;   // tile sites per thread whose rows are read together when staging bonds
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of multiply/xor with the Weyl key
@@ -1149,23 +1150,38 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     const int nw = (n + 31) >> 5;
     if (P > 0) {
       // 1. in-tile partner counts (held in cr until the colours start) and the mask of
-      //    sites that have any, one ballot per 64 consecutive sites
-      for (int ib = 0; ib < n; ib += kBlock) {
-        const int i = ib + tid;
-        int k = 0;
-        if (i < n) {
-          int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
-          row_checked(a, r0, r1);
-          for (int e = r0; e < r1; ++e) {
+      //    sites that have any, one ballot per 64 consecutive sites; kStage sites per
+      //    thread and iteration, their row offsets and first partners read together
+      for (int ib = 0; ib < n; ib += kStage * kBlock) {
+        int r0[kStage], r1[kStage], cf[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const int i = ib + u * kBlock + tid;
+          r0[u] = r1[u] = 0;
+          if (i < n) {
+            r0[u] = a.row_ptr[gt0 + i];
+            r1[u] = a.row_ptr[gt0 + i + 1];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          row_checked(a, r0[u], r1[u]);
+          cf[u] = r1[u] > r0[u] ? a.col[r0[u]] - gt0 : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const int i = ib + u * kBlock + tid;
+          int k = (r1[u] > r0[u] && cf[u] >= 0 && cf[u] < n) ? 1 : 0;
+          for (int e = r0[u] + 1; e < r1[u]; ++e) {
             const int j = a.col[e] - gt0;
             k += (j >= 0 && j < n) ? 1 : 0;
           }
-          t_cr[i] = static_cast<uint16_t>(k);
+          if (i < n) t_cr[i] = static_cast<uint16_t>(k);
+          const uint64_t m = __ballot(k > 0);
+          const int w0 = (ib + u * kBlock + wave * 64) >> 5;
+          if (lane == 0 && w0 < nw) t_bmask[w0] = static_cast<uint32_t>(m);
+          if (lane == 0 && w0 + 1 < nw) t_bmask[w0 + 1] = static_cast<uint32_t>(m >> 32);
         }
-        const uint64_t m = __ballot(k > 0);
-        const int w0 = (ib + wave * 64) >> 5;
-        if (lane == 0 && w0 < nw) t_bmask[w0] = static_cast<uint32_t>(m);
-        if (lane == 0 && w0 + 1 < nw) t_bmask[w0 + 1] = static_cast<uint32_t>(m >> 32);
       }
       __syncthreads();
       // 2. ranks: exclusive prefix of the word popcounts (nw <= 1024 words)
@@ -1215,19 +1231,35 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         if (tid == 0) t_boff[0] = 0;
       }
       __syncthreads();
-      // 4. the partners, in row order
-      for (int i = tid; i < n; i += kBlock) {
-        if (!((t_bmask[i >> 5] >> (i & 31)) & 1u)) continue;
-        const int r = bond_rank(i);
-        if (r >= kBondedCap) continue;
-        const int e_end = t_boff[r + 1];
-        if (e_end > kAdjCap) continue;  // read from global memory when needed
-        int w = t_boff[r];
-        int r0 = a.row_ptr[gt0 + i], r1 = a.row_ptr[gt0 + i + 1];
-        row_checked(a, r0, r1);
-        for (int e = r0; e < r1 && w < e_end; ++e) {
-          const int j = a.col[e] - gt0;
-          if (j >= 0 && j < n) t_adj[w++] = static_cast<uint16_t>(j);
+      // 4. the partners, in row order (kStage sites per thread and iteration, their
+      //    rows read together)
+      for (int ib = 0; ib < n; ib += kStage * kBlock) {
+        int r0[kStage], r1[kStage], wp[kStage], we[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const int i = ib + u * kBlock + tid;
+          r0[u] = r1[u] = wp[u] = 0;
+          we[u] = -1;
+          if (i < n && ((t_bmask[i >> 5] >> (i & 31)) & 1u)) {
+            const int r = bond_rank(i);
+            // rows past the LDS capacity are read from global memory when needed
+            if (r < kBondedCap && t_boff[r + 1] <= kAdjCap) {
+              wp[u] = t_boff[r];
+              we[u] = t_boff[r + 1];
+              r0[u] = a.row_ptr[gt0 + i];
+              r1[u] = a.row_ptr[gt0 + i + 1];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          if (we[u] < 0) continue;
+          row_checked(a, r0[u], r1[u]);
+          int w = wp[u];
+          for (int e = r0[u]; e < r1[u] && w < we[u]; ++e) {
+            const int j = a.col[e] - gt0;
+            if (j >= 0 && j < n) t_adj[w++] = static_cast<uint16_t>(j);
+          }
         }
       }
       __syncthreads();
