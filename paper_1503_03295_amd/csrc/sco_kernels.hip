@@ -1149,11 +1149,12 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     const int y0 = idiv_fp(v0, K.inv_L), x0 = v0 - y0 * L;
     const int nw = (n + 31) >> 5;
     if (P > 0) {
-      // 1. in-tile partner counts (held in cr until the colours start) and the mask of
-      //    sites that have any, one ballot per 64 consecutive sites; kStage sites per
-      //    thread and iteration, their row offsets and first partners read together
+      // 1. row lengths (held in cr until the colours start) and the mask of sites with
+      //    bonds, one ballot per 64 consecutive sites; kStage sites per thread and
+      //    iteration, their row offsets read together.  A partner outside the tile is
+      //    kept in the lists as a mark the visits skip.
       for (int ib = 0; ib < n; ib += kStage * kBlock) {
-        int r0[kStage], r1[kStage], cf[kStage];
+        int r0[kStage], r1[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
           const int i = ib + u * kBlock + tid;
@@ -1165,17 +1166,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          row_checked(a, r0[u], r1[u]);
-          cf[u] = r1[u] > r0[u] ? a.col[r0[u]] - gt0 : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < kStage; ++u) {
           const int i = ib + u * kBlock + tid;
-          int k = (r1[u] > r0[u] && cf[u] >= 0 && cf[u] < n) ? 1 : 0;
-          for (int e = r0[u] + 1; e < r1[u]; ++e) {
-            const int j = a.col[e] - gt0;
-            k += (j >= 0 && j < n) ? 1 : 0;
-          }
+          row_checked(a, r0[u], r1[u]);
+          const int k = min(r1[u] - r0[u], 65535);
           if (i < n) t_cr[i] = static_cast<uint16_t>(k);
           const uint64_t m = __ballot(k > 0);
           const int w0 = (ib + u * kBlock + wave * 64) >> 5;
@@ -1205,7 +1198,10 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       for (int i = tid; i < n; i += kBlock)
         if ((t_bmask[i >> 5] >> (i & 31)) & 1u) {
           const int r = bond_rank(i);
-          if (r < kBondedCap) t_boff[r + 1] = t_cr[i];
+          if (r < kBondedCap) {
+            t_boff[r + 1] = t_cr[i];
+            t_list[r] = static_cast<uint16_t>(i);  // the r-th bonded site (list unused until the levels)
+          }
         }
       __syncthreads();
       {
@@ -1231,24 +1227,22 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         if (tid == 0) t_boff[0] = 0;
       }
       __syncthreads();
-      // 4. the partners, in row order (kStage sites per thread and iteration, their
-      //    rows read together)
-      for (int ib = 0; ib < n; ib += kStage * kBlock) {
+      // 4. the partners, in row order, of the bonded sites by rank (kStage per thread
+      //    and iteration, their rows read together); 0xFFFF marks one outside the tile
+      for (int rb = 0; rb < nb; rb += kStage * kBlock) {
         int r0[kStage], r1[kStage], wp[kStage], we[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          const int i = ib + u * kBlock + tid;
+          const int r = rb + u * kBlock + tid;
           r0[u] = r1[u] = wp[u] = 0;
           we[u] = -1;
-          if (i < n && ((t_bmask[i >> 5] >> (i & 31)) & 1u)) {
-            const int r = bond_rank(i);
-            // rows past the LDS capacity are read from global memory when needed
-            if (r < kBondedCap && t_boff[r + 1] <= kAdjCap) {
-              wp[u] = t_boff[r];
-              we[u] = t_boff[r + 1];
-              r0[u] = a.row_ptr[gt0 + i];
-              r1[u] = a.row_ptr[gt0 + i + 1];
-            }
+          // rows past the LDS capacity are read from global memory when needed
+          if (r < nb && t_boff[r + 1] <= kAdjCap) {
+            const int i = t_list[r];
+            wp[u] = t_boff[r];
+            we[u] = t_boff[r + 1];
+            r0[u] = a.row_ptr[gt0 + i];
+            r1[u] = a.row_ptr[gt0 + i + 1];
           }
         }
 #pragma unroll
@@ -1258,7 +1252,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
           int w = wp[u];
           for (int e = r0[u]; e < r1[u] && w < we[u]; ++e) {
             const int j = a.col[e] - gt0;
-            if (j >= 0 && j < n) t_adj[w++] = static_cast<uint16_t>(j);
+            t_adj[w++] = (j >= 0 && j < n) ? static_cast<uint16_t>(j) : static_cast<uint16_t>(0xFFFF);
           }
         }
       }
