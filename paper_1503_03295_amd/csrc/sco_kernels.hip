@@ -33,6 +33,10 @@ constexpr int kBatch = 3;
 constexpr int kScan = 4;
 constexpr int kOwners = 2;  // owners in flight per thread in the switching
 constexpr int kStage = 8;   // tile sites per thread whose rows are read together when staging bonds
+// Sites per thread whose colours stay in registers while a block buckets them: a
+// device-wide level's share and a sweep range of a 2304^2 lattice over 256 blocks.
+constexpr int kHeldKW = 12;
+constexpr int kHeldSw = 21;
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of multiply/xor with the Weyl key
@@ -349,6 +353,13 @@ struct ColorSet {
 };
 
 // The same for palettes of at most 64 colours (every colour stored is below q).
+struct ColorSet32 {
+  uint32_t w = 0;
+  __device__ __forceinline__ void add(int c) { w |= 1u << (c & 31); }
+  __device__ __forceinline__ void add_if(bool on, int c) { w |= on ? 1u << (c & 31) : 0u; }
+  __device__ __forceinline__ int first_free() const { return ~w ? __ffs(~w) - 1 : 32; }
+};
+
 struct ColorSet64 {
   uint64_t w = 0;
   __device__ __forceinline__ void add(int c) { w |= 1ull << (c & 63); }
@@ -1324,7 +1335,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         int tmax = 0;
         int cls = q - 1;  // class of the lane's current position (only decreases)
         bool have = false, more = true;
-        int i = 0, cl = 0, grp = 0;
+        int i = 0, cl = 0;
+        int glo = 0, gmid = 0, ghi = 0;  // the site's group at this level: [glo, ghi), pending from gmid
         int jt[4] = {-1, -1, -1, -1};
         int e0 = 0, e1 = 0, g0 = 0, g1 = 0;  // in-tile bonds in LDS, or the row in memory
         for (uint32_t spin = 0;; ++spin) {
@@ -1345,7 +1357,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
                 while (kx < t_off[cls]) --cls;
                 cl = cls;
                 i = t_list[kx];
-                grp = div16(i, mq) >> p;
+                glo = static_cast<int>(__umul24(div16(i, mq) >> p, 2 * H));
+                gmid = glo + H;
+                ghi = min(glo + 2 * H, n);
                 const int t = x0 + i, dy = div16(t, mL);
                 int nb[4];
                 nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
@@ -1378,12 +1392,10 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
             // neighbour j (tile index, -1 for none) with word w: same group only; a
             // pending one counts once decided and one of a higher class must be
             auto visit_w = [&](int jn, int w) {
-              const bool in = jn >= 0 && jn < n;  // outside the tile: another group
-              const int jj = in ? jn : i;
-              const int gj = div16(jj, mq);
-              const bool pend = (gj >> (p - 1)) & 1;
+              // outside the tile (negative, or 0xFFFF from the adjacency) is another group
+              const bool same = jn >= glo && jn < ghi;
+              const bool pend = jn >= gmid;
               const int rj = w >> 8;
-              const bool same = in && (gj >> p) == grp;
               const bool on = same && (!pend || rj != 0);
               const int cj = w & 0xFF;
               ready = ready && !(same && pend && rj == 0 && cj > cl && cj < q);
@@ -1426,7 +1438,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         tmax = wave_max(tmax);
         if (lane == 0 && tmax > 0) atomicMax(&t_rounds, tmax);
       };
-      if (q <= 64) run_classes(ColorSet64{});
+      if (q <= 32) run_classes(ColorSet32{});
+      else if (q <= 64) run_classes(ColorSet64{});
       else run_classes(ColorSet{});
       __syncthreads();
       if (threadIdx.x == 0 && t_rounds > 0) atomicMax(&a.st[c].kw_rounds[p], t_rounds);
@@ -1509,6 +1522,11 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       const uint32_t j = static_cast<uint32_t>(idiv_fp(static_cast<int>(kk >> (p - 1)), ks.kc[c].inv_q));
       v = static_cast<int>((2u * j + 1u) * h + (kk - j * h));
     };
+    auto site_chain = [&](long long k) {
+      int c, v;
+      site_of(k, c, v);
+      return c;
+    };
     auto bucket = [&](int32_t* lst) __attribute__((always_inline)) {
       for (int pass = 0; pass < 2; ++pass) {
         // kScan sites per thread and iteration, their loads issued together
@@ -1548,8 +1566,50 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
         }
       }
     };
-    if (in_lds) bucket(lds_list);
-    else bucket(lst_mem);
+    // a share of at most kHeldKW sites per thread: every colour loaded at once and kept
+    // in registers between the count and the scatter
+    auto bucket_held = [&](int32_t* lst) __attribute__((always_inline)) {
+      // the word of each site, or ~0 for none; the palette check goes by the chain's q
+      uint32_t wd[kHeldKW];
+#pragma unroll
+      for (int r = 0; r < kHeldKW; ++r) {
+        const long long k = k0 + r * kBlock + tid;
+        wd[r] = ~0u;
+        if (k < k1) {
+          int c, v;
+          site_of(k, c, v);
+          wd[r] = ld_global(&a.kw_word[ks.kc[c].vbase + v]) & 0x1FFu;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kHeldKW; ++r) {
+        if (wd[r] == ~0u) continue;
+        const int cc = static_cast<int>(wd[r]);
+        if (cc >= qmax || (nch > 1 && cc >= ks.kc[site_chain(k0 + r * kBlock + tid)].q)) {
+          set_flag(a.sync, SCO_FLAG_PALETTE);  // cannot happen after a complete colouring
+          wd[r] = ~0u;
+          continue;
+        }
+        atomicAdd(&boff[cc + 1], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
+      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kHeldKW; ++r)
+        if (wd[r] != ~0u) lst[boff[wd[r]] + atomicAdd(&bfill[wd[r]], 1)] = r * kBlock + tid;
+      __syncthreads();
+    };
+    if (k1 - k0 <= static_cast<long long>(kHeldKW) * kBlock) {
+      if (in_lds) bucket_held(lds_list);
+      else bucket_held(lst_mem);
+    } else if (in_lds) {
+      bucket(lds_list);
+    } else {
+      bucket(lst_mem);
+    }
     mark(a.trace, 200 + p);
     // The classes run without a barrier between them.  A pending site of class cc
     // reads the colours its same-group pending neighbours of higher classes take at
@@ -1734,8 +1794,41 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   // The list in LDS and the chain descriptors in LDS (the usual case), or both in
   // global memory: two inlined copies, so LDS accesses stay LDS instructions.
   auto body = [&](int32_t* lst, const auto& desc) __attribute__((always_inline)) -> bool {
-    // colour buckets of the block's sites: count, offsets, list (kScan sites per thread
-    // and iteration, their loads issued together)
+    // colour buckets of the block's sites: count, offsets, list.  A range of at most
+    // kHeldSw sites per thread loads every colour at once and keeps them in registers;
+    // a longer one takes two passes of kScan sites per thread and iteration.
+    if (r1 - r0 <= static_cast<int64_t>(kHeldSw) * kBlock) {
+      int col[kHeldSw];
+#pragma unroll
+      for (int r = 0; r < kHeldSw; ++r) {
+        const int64_t g = r0 + r * kBlock + tid;
+        col[r] = -1;  // no site
+        if (g < r1) {
+          const int c = c_lo == c_hi ? c_lo : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+          const ChainDesc& d = desc(c);
+          if (static_cast<int>(g - d.vbase) < d.N) col[r] = a.color[g];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kHeldSw; ++r) {
+        if (col[r] < 0) continue;
+        if (col[r] >= qmax) {  // cannot happen after a complete colouring
+          set_flag(a.sync, SCO_FLAG_PALETTE);
+          col[r] = -1;
+          continue;
+        }
+        atomicAdd(&boff[col[r] + 1], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
+      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kHeldSw; ++r)
+        if (col[r] >= 0) lst[boff[col[r]] + atomicAdd(&bfill[col[r]], 1)] = r * kBlock + tid;
+      __syncthreads();
+    } else
     for (int pass = 0; pass < 2; ++pass) {
       for (int64_t gb = r0; gb < r1; gb += kScan * kBlock) {
         int col[kScan];
