@@ -37,6 +37,15 @@ constexpr int kStage = 8;   // tile sites per thread whose rows are read togethe
 // device-wide level's share and a sweep range of a 2304^2 lattice over 256 blocks.
 constexpr int kHeldKW = 12;
 constexpr int kHeldSw = 21;
+// Spin words (4 sites each) per thread when a block stages its own sweep range in LDS,
+// and halo bytes per thread (two rows of up to 2560 sites).
+constexpr int kStageSw = 6;
+constexpr int kHaloSw = 5;
+
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of multiply/xor with the Weyl key
@@ -56,6 +65,26 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     c1 = lo1;
     c2 = n2;
     c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return W4{c0, c1, c2, c3};
+}
+
+// The same generator with each 32 x 32 -> 64-bit product taken whole (one
+// multiply-add instruction instead of a low and a high multiply).
+__device__ __forceinline__ W4 philox10_wide(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = static_cast<uint32_t>(p1);
+    c2 = n2;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -1793,7 +1822,12 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   __syncthreads();
   // The list in LDS and the chain descriptors in LDS (the usual case), or both in
   // global memory: two inlined copies, so LDS accesses stay LDS instructions.
-  auto body = [&](int32_t* lst, const auto& desc) __attribute__((always_inline)) -> bool {
+  // staged: the block's range is one chain, and its spins with one lattice row on
+  // either side are held in LDS after the list (bit 0: spin up; bit 1: the site has
+  // bonds).  A class reads its lattice neighbours there; only the two halo rows,
+  // which other blocks update, are read again from global memory before each class.
+  auto body = [&](int32_t* lst, const auto& desc, auto staged_tag) __attribute__((always_inline)) -> bool {
+    constexpr bool staged = decltype(staged_tag)::value;
     // colour buckets of the block's sites: count, offsets, list.  A range of at most
     // kHeldSw sites per thread loads every colour at once and keeps them in registers;
     // a longer one takes two passes of kScan sites per thread and iteration.
@@ -1867,9 +1901,76 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
     }
     mark(a.trace, 22);
 
+    // tile slot t holds chain-local site tl_base + t (wrapped on a periodic lattice);
+    // the own range is slots [L, L + n_own)
+    int8_t* const tile = reinterpret_cast<int8_t*>(lst + (r1 - r0));
+    const int n_own = static_cast<int>(r1 - r0);
+    const int tl_L = staged ? desc(c_lo).L : 0;
+    const int tl_N = staged ? desc(c_lo).N : 0;
+    const int64_t tl_vb = staged ? desc(c_lo).vbase : 0;
+    const int tl_base = static_cast<int>(r0 - tl_vb) - tl_L;
+    const bool tl_per = staged && desc(c_lo).periodic != 0;
+    // the two halo rows, one coherent byte read per site
+    auto load_halo = [&]() __attribute__((always_inline)) {
+      int hv[kHaloSw];
+#pragma unroll
+      for (int r = 0; r < kHaloSw; ++r) {
+        const int t = r * kBlock + tid;
+        hv[r] = -1;
+        if (t < 2 * tl_L) {
+          int u = tl_base + (t < tl_L ? t : t + n_own);
+          if (tl_per) u = u < 0 ? u + tl_N : (u >= tl_N ? u - tl_N : u);
+          if (u >= 0 && u < tl_N) hv[r] = ld_relaxed(&a.spin[tl_vb + u]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kHaloSw; ++r) {
+        const int t = r * kBlock + tid;
+        if (t < 2 * tl_L) tile[t < tl_L ? t : t + n_own] = static_cast<int8_t>(hv[r] > 0 ? 1 : 0);
+      }
+    };
+    if constexpr (staged) {
+      // own range, four sites per word read (the range and the chain start on chunk
+      // bounds); a site has bonds when its degree is not zero
+      uint32_t sw[kStageSw];
+      int4 dg[kStageSw];
+#pragma unroll
+      for (int r = 0; r < kStageSw; ++r) {
+        const int w = r * kBlock + tid;
+        sw[r] = 0u;
+        dg[r] = make_int4(0, 0, 0, 0);
+        if (4 * w < n_own) {
+          sw[r] = ld_relaxed(reinterpret_cast<const uint32_t*>(a.spin + r0) + w);
+          dg[r] = reinterpret_cast<const int4*>(a.deg + r0)[w];
+        }
+      }
+      load_halo();
+#pragma unroll
+      for (int r = 0; r < kStageSw; ++r) {
+        const int w = r * kBlock + tid;
+        if (4 * w < n_own) {
+          const int dd[4] = {dg[r].x, dg[r].y, dg[r].z, dg[r].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int8_t sp = static_cast<int8_t>((sw[r] >> (8 * i)) & 0xFFu);
+            tile[tl_L + 4 * w + i] = static_cast<int8_t>((sp > 0 ? 1 : 0) | (dd[i] != 0 ? 2 : 0));
+          }
+        }
+      }
+      __syncthreads();
+    }
+
     for (int s = 0; s < a.nsw_max; ++s) {
       for (int cc = 0; cc < qmax; ++cc) {
         const int k0 = boff[cc], k1 = boff[cc + 1];
+        if constexpr (staged) {
+          // the halo rows as the previous class left them (the first class of the
+          // first sweep has them from the staging)
+          if (s > 0 || cc > 0) {
+            load_halo();
+            __syncthreads();
+          }
+        }
         // every thread of the block runs the same number of iterations; each takes
         // kBatch sites of the class and loads their neighbour spins before deciding
         // (sites of one class are not coupled)
@@ -1895,13 +1996,35 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
                 int nb[4];
                 nn_sites(x, y, d.L, d.periodic, nb);
+                if constexpr (staged) {
+                  // a neighbour's slot: its offset from v taken the short way round
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                  if (nb[t] >= 0) nsum[r] += ld_relaxed(&a.spin[d.vbase + nb[t]]);
-                sv[r] = ld_relaxed(&a.spin[gs[r]]);
-                q0[r] = a.row_ptr[gs[r]];
-                q1[r] = a.row_ptr[gs[r] + 1];
-                row_checked(a, q0[r], q1[r]);
+                  for (int t = 0; t < 4; ++t)
+                    if (nb[t] >= 0) {
+                      int dv = nb[t] - v;
+                      dv = dv > tl_N / 2 ? dv - tl_N : (dv < -(tl_N / 2) ? dv + tl_N : dv);
+                      nsum[r] += (tile[v + dv - tl_base] & 1) ? 1 : -1;
+                    }
+                  const int b = tile[v - tl_base];
+                  sv[r] = (b & 1) ? 1 : -1;
+                  if (b & 2) {
+                    if (d.hard) {
+                      q1[r] = 1;  // any bond is hard: the flip is refused without its row
+                    } else {
+                      q0[r] = a.row_ptr[gs[r]];
+                      q1[r] = a.row_ptr[gs[r] + 1];
+                      row_checked(a, q0[r], q1[r]);
+                    }
+                  }
+                } else {
+#pragma unroll
+                  for (int t = 0; t < 4; ++t)
+                    if (nb[t] >= 0) nsum[r] += ld_relaxed(&a.spin[d.vbase + nb[t]]);
+                  sv[r] = ld_relaxed(&a.spin[gs[r]]);
+                  q0[r] = a.row_ptr[gs[r]];
+                  q1[r] = a.row_ptr[gs[r] + 1];
+                  row_checked(a, q0[r], q1[r]);
+                }
               }
             }
           }
@@ -1920,7 +2043,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 if (pa >= 1.0) {
                   acc[r] = true;
                 } else {
-                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                  const W4 w = philox10_wide(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                         d.seed, d.chain_id);
                   acc[r] = unit52(w.x, w.y) < pa;
                 }
@@ -1947,7 +2070,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 if (dE <= -errE) {
                   acc[r] = done = true;
                 } else if (dE > errE) {
-                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                  const W4 w = philox10_wide(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                         d.seed, d.chain_id);
                   const double u = unit52(w.x, w.y);
                   const float x = d.neg_beta32 * dE;
@@ -1974,7 +2097,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 if (dE <= 0.0) {
                   acc[r] = true;
                 } else {
-                  const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
+                  const W4 w = philox10_wide(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                         d.seed, d.chain_id);
                   const double u = unit52(w.x, w.y);
                   const double pr = exp(d.neg_beta * dE);
@@ -1983,7 +2106,10 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 }
               }
             }
-            if (acc[r]) st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
+            if (acc[r]) {
+              st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
+              if constexpr (staged) tile[v - tl_base] ^= 1;
+            }
           }
           // accepted flips per chain into LDS: one atomic per wave when the wave is one chain
 #pragma unroll
@@ -2007,9 +2133,20 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
     }
     return true;
   };
-  const bool ok = (local_cd && r1 - r0 <= kListCap)
-                      ? body(lds_list, [&](int c) -> const ChainDesc& { return lcd[c - c_lo]; })
-                      : body(lst_mem, [&](int c) -> const ChainDesc& { return a.cd[c]; });
+  auto ldesc = [&](int c) -> const ChainDesc& { return lcd[c - c_lo]; };
+  // staging needs one chain and a range that ends inside it (a wrapped neighbour of
+  // the last row is then a halo slot, never a padding site), a lattice of at least
+  // 8 x 8, the halo rows within kHaloSw bytes per thread, the range within kStageSw
+  // words per thread, and room for list and tile
+  const bool staged_ok =
+      local_cd && c_lo == c_hi && r0 < r1 && r1 - lcd[0].vbase <= lcd[0].N && lcd[0].L >= 8 &&
+      2 * lcd[0].L <= kHaloSw * kBlock &&
+      (r1 - r0) % 4 == 0 && r1 - r0 <= 4 * kStageSw * kBlock &&
+      4 * (r1 - r0) + (r1 - r0) + 2 * lcd[0].L <= static_cast<int64_t>(sizeof(int32_t)) * kListCap;
+  bool ok;
+  if (staged_ok) ok = body(lds_list, ldesc, Flag<true>{});
+  else if (local_cd && r1 - r0 <= kListCap) ok = body(lds_list, ldesc, Flag<false>{});
+  else ok = body(lst_mem, [&](int c) -> const ChainDesc& { return a.cd[c]; }, Flag<false>{});
   if (!ok) return false;
   for (int c = tid; c < a.n_chains; c += kBlock)
     if (bacc[c]) atomicAdd(&a.st[c].accepted, bacc[c]);
