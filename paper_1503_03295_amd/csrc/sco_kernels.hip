@@ -916,33 +916,41 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
 }
 
 // Sorts each row ascending by neighbour; union degree |CSR(v) u NN(v)|; Delta and
-// directed bond count per chain.  Block b takes a contiguous range of chunks, kScan
-// chunks per iteration with their row offsets loaded together; the per-chain maximum
-// and sum gather in LDS (one atomic per wave when the wave is one chain) and reach
-// the chain states once per block.
-__device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
+// directed bond count per chain.  Block b takes a contiguous range of chunks.  When
+// every site of the range fits the LDS queue (q_cap entries), a first pass reads only the row
+// offsets (kScanRow chunks per iteration): an empty row, the usual case, has its
+// lattice neighbour count as union degree, and the sites with bonds are queued; a
+// second pass reads, sorts and checks the queued rows.  Otherwise each site takes the
+// full path, kScan chunks per iteration.  The per-chain maximum and sum gather in LDS
+// (one atomic per wave when the wave is one chain) and reach the chain states once
+// per block.
+constexpr int kScanRow = 8;
+__device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q, int q_cap) {
   __shared__ int32_t rmax[SCO_MAXCHAINS];
   __shared__ int32_t rsum[SCO_MAXCHAINS];
+  __shared__ int32_t s_nq;
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) rmax[c] = rsum[c] = 0;
+  if (threadIdx.x == 0) s_nq = 0;
   __syncthreads();
-  for (int chb = ch0; chb < ch1; chb += kScan) {
+  // the full path for up to kScan sites per thread (g < 0: none): row read in one
+  // round, sorted in registers when short (nearly all), union degree against the
+  // lattice neighbours
+  auto full_rows = [&](const int64_t (&gs)[kScan]) __attribute__((always_inline)) {
     int cs[kScan], r0[kScan], r1[kScan];
     bool ok[kScan];
 #pragma unroll
     for (int r = 0; r < kScan; ++r) {
-      const int ch = chb + r;
       ok[r] = false;
       cs[r] = -1;
       r0[r] = r1[r] = 0;
-      if (ch < ch1) {
-        cs[r] = a.chunk_chain[ch];
-        const int64_t g = (static_cast<int64_t>(ch) << SCO_CHUNK_SHIFT) + threadIdx.x;
-        ok[r] = static_cast<int>(g - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
+      if (gs[r] >= 0) {
+        cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
+        ok[r] = static_cast<int>(gs[r] - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
         if (ok[r]) {
-          r0[r] = a.row_ptr[g];
-          r1[r] = a.row_ptr[g + 1];
+          r0[r] = a.row_ptr[gs[r]];
+          r1[r] = a.row_ptr[gs[r] + 1];
         }
       }
     }
@@ -966,8 +974,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
       int udeg = 0, rowlen = 0;
       if (ok[r]) {
         const ChainDesc& d = a.cd[cs[r]];
-        const int64_t g = (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x;
-        const int v = static_cast<int>(g - d.vbase);
+        const int v = static_cast<int>(gs[r] - d.vbase);
         const int q0 = r0[r], q1 = r1[r];
         rowlen = q1 - q0;
         const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
@@ -1028,6 +1035,76 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a) {
       const int c = ok[r] ? cs[r] : -1;
       wave_max_to(rmax, c, udeg);
       wave_sum_to(rsum, c, rowlen);
+    }
+  };
+  const bool queued = static_cast<int64_t>(ch1 - ch0) * kBlock <= q_cap;
+  if (queued) {
+    const uint32_t lane = lane_id();
+    for (int chb = ch0; chb < ch1; chb += kScanRow) {
+      int cs[kScanRow], r0[kScanRow], r1[kScanRow];
+      bool ok[kScanRow];
+#pragma unroll
+      for (int r = 0; r < kScanRow; ++r) {
+        const int ch = chb + r;
+        ok[r] = false;
+        cs[r] = -1;
+        r0[r] = r1[r] = 0;
+        if (ch < ch1) {
+          cs[r] = a.chunk_chain[ch];
+          const int64_t g = (static_cast<int64_t>(ch) << SCO_CHUNK_SHIFT) + threadIdx.x;
+          ok[r] = static_cast<int>(g - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
+          if (ok[r]) {
+            r0[r] = a.row_ptr[g];
+            r1[r] = a.row_ptr[g + 1];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kScanRow; ++r) {
+        const int64_t g = (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x;
+        if (ok[r]) row_checked(a, r0[r], r1[r]);
+        const bool push = ok[r] && r1[r] > r0[r];
+        const uint64_t pm = __ballot(push);
+        if (pm != 0) {
+          const int leader = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+          int base = 0;
+          if (static_cast<int>(lane) == leader) base = atomicAdd(&s_nq, __popcll(pm));
+          base = __shfl(base, leader);
+          if (push) lds_q[base + __popcll(pm & ((1ull << lane) - 1ull))] = static_cast<int32_t>(g);
+        }
+        // an empty row: the union degree is the number of lattice neighbours
+        int udeg = 0;
+        if (ok[r] && !push) {
+          const ChainDesc& d = a.cd[cs[r]];
+          if (d.periodic) {
+            udeg = 4;
+          } else {
+            const int v = static_cast<int>(g - d.vbase);
+            const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
+            udeg = (x + 1 < d.L) + (x > 0) + (y + 1 < d.L) + (y > 0);
+          }
+        }
+        wave_max_to(rmax, ok[r] && !push ? cs[r] : -1, udeg);
+      }
+    }
+    __syncthreads();
+    const int nq = s_nq;
+    for (int qb = 0; qb < nq; qb += kScan * kBlock) {
+      int64_t gs[kScan];
+#pragma unroll
+      for (int r = 0; r < kScan; ++r) {
+        const int k = qb + r * kBlock + static_cast<int>(threadIdx.x);
+        gs[r] = k < nq ? static_cast<int64_t>(lds_q[k]) : -1;
+      }
+      full_rows(gs);
+    }
+  } else {
+    for (int chb = ch0; chb < ch1; chb += kScan) {
+      int64_t gs[kScan];
+#pragma unroll
+      for (int r = 0; r < kScan; ++r)
+        gs[r] = chb + r < ch1 ? (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x : -1;
+      full_rows(gs);
     }
   }
   __syncthreads();
@@ -2196,7 +2273,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     phase_scatter(a);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 5);
-    phase_rowsort(a);
+    phase_rowsort(a, lds.list, kListCap);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 6);
     if (lead) a.sync->graph_valid = 1;
