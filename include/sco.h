@@ -27,7 +27,10 @@
  *     coexist; they share nothing.
  *   - Return value: SCO_OK (0) or a negative SCO_E* code; sco_strerror() names it.
  *     Device-side conditions (edge capacity exceeded, a bounded wait that timed
- *     out) are raised as flags and reported by the next synchronising call.
+ *     out, palette overflow, a broken graph state) are raised as flags.  The launch
+ *     that raises one ends at its next device-wide barrier, before its step moves any
+ *     spin, and later launches do nothing until the next synchronising call reports
+ *     the flag (SCO_EOVERFLOW, SCO_ETIMEOUT, SCO_EPALETTE, SCO_EINTERNAL) and clears it.
  *   - Sites are numbered row-major, v = y * L + x; spins are int8 +1 / -1.
  *   - Randomness: Philox4x32-10 (Salmon et al., SC'11), key (seed, chain_id),
  *     counter (step, site, draw, tag).  A chain is a pure function of its
@@ -47,8 +50,12 @@ extern "C" {
 #define SCO_EINVAL (-1)    /* invalid argument or parameter */
 #define SCO_EHIP (-2)      /* a HIP runtime call failed */
 #define SCO_EOVERFLOW (-3) /* surviving bonds exceeded the edge capacity: the step is invalid */
-#define SCO_EINTERNAL (-4) /* an invariant failed or a bounded device wait timed out */
+#define SCO_EINTERNAL (-4) /* an invariant failed: a colouring or sweep launched without a valid
+                              bond graph, or a CSR row outside the edge arrays */
 #define SCO_ENOSPC (-5)    /* the workspace is smaller than sco_workspace_size() */
+#define SCO_ETIMEOUT (-6)  /* a bounded device wait ran out (the persistent kernel's blocks were
+                              not all resident); the chain state is that before the failed step */
+#define SCO_EPALETTE (-7)  /* the union graph needs more than 255 colours (Delta + 1 > 255) */
 
 /* Parameters of one Markov chain. */
 typedef struct {
@@ -84,6 +91,10 @@ typedef struct {
   int64_t flags;      /* device flags seen since the last counter reset: bit 0 edge
                          overflow, bit 1 wait timeout, bit 2 palette overflow,
                          bit 3 colouring or sweep launched without a valid graph */
+  int64_t near_ties;  /* decisions whose two compared FP64 numbers lay within 1e-12 of each
+                         other: switching targets within 1e-12 relative of C_top or of a
+                         bracketing cumulative coupling, Metropolis draws |u - p| < 1e-12
+                         (the only decisions a host evaluation may take differently) */
 } sco_obs;
 
 typedef struct sco_ctx sco_ctx;
@@ -114,8 +125,15 @@ int sco_sweep(sco_ctx* ctx, uint64_t step, int n_sw);
 /* Steps (1)-(3) with each chain's own n_sw. */
 int sco_step(sco_ctx* ctx, uint64_t step);
 
-/* Runs steps first_step .. first_step + n_steps - 1 back to back. */
+/* Runs steps first_step .. first_step + n_steps - 1 back to back, then synchronises
+ * and reports any device flag raised by them (a step that raises one ends at its next
+ * device-wide barrier and the launches after it do nothing, so the spins are those
+ * before the failed step). */
 int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
+
+/* Device flags (SCO_FLAG bits as in sco_obs.flags) of the last flagged launch that a
+ * synchronising call consumed, and all flags seen since the last counter reset. */
+int sco_get_flags(sco_ctx* ctx, int64_t* last, int64_t* seen);
 
 /* Observables of every chain into host_out[n_chains]; synchronises. */
 int sco_observables(sco_ctx* ctx, sco_obs* host_out);

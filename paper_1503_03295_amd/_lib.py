@@ -8,12 +8,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsco.so")
 
 SCO_OK, SCO_EINVAL, SCO_EHIP, SCO_EOVERFLOW, SCO_EINTERNAL, SCO_ENOSPC = 0, -1, -2, -3, -4, -5
+SCO_ETIMEOUT, SCO_EPALETTE = -6, -7
+FLAG_NAMES = {1: "edge overflow", 2: "wait timeout", 4: "palette overflow", 8: "graph state"}
 
 EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
-    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune",
+    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags",
 ]
 
 
@@ -35,17 +37,23 @@ class ObsC(ctypes.Structure):
         ("delta_union", ctypes.c_int32), ("q", ctypes.c_int32), ("colors_used", ctypes.c_int32),
         ("kw_levels", ctypes.c_int32),
         ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
-        ("rechecks", ctypes.c_int64), ("flags", ctypes.c_int64),
+        ("rechecks", ctypes.c_int64), ("flags", ctypes.c_int64), ("near_ties", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+def flag_names(flags: int) -> str:
+    return ", ".join(n for b, n in FLAG_NAMES.items() if flags & b) or "none"
+
+
 class ScoError(RuntimeError):
-    def __init__(self, code: int, what: str):
+    def __init__(self, code: int, what: str, flags: int | None = None):
         self.code = code
-        super().__init__(f"{what}: {lib().sco_strerror(code).decode()} ({code})")
+        self.flags = flags
+        extra = f"; device flags {flags:#x} ({flag_names(flags)})" if flags else ""
+        super().__init__(f"{what}: {lib().sco_strerror(code).decode()} ({code}){extra}")
 
 
 _lib = None
@@ -80,6 +88,7 @@ def lib():
         "sco_trace_read": ([P, P, P, i32, ctypes.POINTER(ctypes.c_int)], i32),
         "sco_reset_counters": ([P], i32),
         "sco_destroy": ([P], i32),
+        "sco_get_flags": ([P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
         "sco_strerror": ([i32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -90,6 +99,13 @@ def lib():
     return L
 
 
-def check(code: int, what: str) -> None:
+def check(code: int, what: str, ctx=None) -> None:
+    """Raises ScoError for a non-zero code; with a context, the error names the device
+    flags of the failed launch."""
     if code != SCO_OK:
-        raise ScoError(code, what)
+        flags = None
+        if ctx:
+            last = ctypes.c_int64(0)
+            if lib().sco_get_flags(ctx, ctypes.byref(last), None) == SCO_OK:
+                flags = int(last.value)
+        raise ScoError(code, what, flags)

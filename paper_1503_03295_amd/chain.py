@@ -89,30 +89,30 @@ class SCO:
 
     # -- the step
     def switch(self, step: int) -> None:
-        check(lib().sco_switch(self._h, step), "sco_switch")
+        check(lib().sco_switch(self._h, step), "sco_switch", self._h)
 
     def color(self) -> None:
-        check(lib().sco_color(self._h), "sco_color")
+        check(lib().sco_color(self._h), "sco_color", self._h)
 
     def sweep(self, step: int, n_sw: int) -> None:
-        check(lib().sco_sweep(self._h, step, n_sw), "sco_sweep")
+        check(lib().sco_sweep(self._h, step, n_sw), "sco_sweep", self._h)
 
     def step(self, step: int) -> None:
-        check(lib().sco_step(self._h, step), "sco_step")
+        check(lib().sco_step(self._h, step), "sco_step", self._h)
 
     def run(self, first_step: int, n_steps: int) -> None:
-        check(lib().sco_run(self._h, first_step, n_steps), "sco_run")
+        check(lib().sco_run(self._h, first_step, n_steps), "sco_run", self._h)
 
     # -- results
     def observables(self) -> list[dict]:
         out = (ObsC * self.n_chains)()
-        check(lib().sco_observables(self._h, out), "sco_observables")
+        check(lib().sco_observables(self._h, out), "sco_observables", self._h)
         return [o.as_dict() for o in out]
 
     def spins(self, chain: int = 0) -> np.ndarray:
         p = self.params[chain]
         out = np.empty(p.L * p.L, np.int8)
-        check(lib().sco_get_spins(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)), "sco_get_spins")
+        check(lib().sco_get_spins(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)), "sco_get_spins", self._h)
         return out
 
     def set_spins(self, chain: int, spins: np.ndarray) -> None:
@@ -120,56 +120,56 @@ class SCO:
         p = self.params[chain]
         if a.size != p.L * p.L:
             raise ValueError("wrong number of spins")
-        check(lib().sco_set_spins(self._h, chain, a.ctypes.data_as(ctypes.c_void_p)), "sco_set_spins")
+        check(lib().sco_set_spins(self._h, chain, a.ctypes.data_as(ctypes.c_void_p)), "sco_set_spins", self._h)
 
     def graph(self, chain: int = 0):
         p = self.params[chain]
         N = p.L * p.L
         nd = ctypes.c_int64(0)
-        check(lib().sco_get_graph(self._h, chain, None, None, None, None, ctypes.byref(nd)), "sco_get_graph")
+        check(lib().sco_get_graph(self._h, chain, None, None, None, None, ctypes.byref(nd)), "sco_get_graph", self._h)
         rp = np.empty(N + 1, np.int32)
         col = np.empty(max(nd.value, 1), np.int32)
         at = np.empty(max(nd.value, 1), np.int32)
         colors = np.empty(N, np.int32)
         ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
         check(lib().sco_get_graph(self._h, chain, ptr(rp), ptr(col), ptr(at), ptr(colors), ctypes.byref(nd)),
-              "sco_get_graph")
+              "sco_get_graph", self._h)
         return rp, col[: nd.value], at[: nd.value], colors
 
     def tables(self, chain: int = 0) -> dict:
         K = ctypes.c_int32(0)
         check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), None, None, None, None, None, None),
-              "sco_get_tables")
+              "sco_get_tables", self._h)
         n = K.value
         dx = np.empty(n, np.int32); dy = np.empty(n, np.int32)
         J = np.empty(n); C = np.empty(n); th = np.empty(n); de = np.empty(n)
         ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
         check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), ptr(dx), ptr(dy), ptr(J), ptr(C),
-                                   ptr(th), ptr(de)), "sco_get_tables")
+                                   ptr(th), ptr(de)), "sco_get_tables", self._h)
         return {"dx": dx, "dy": dy, "J": J, "C": C, "theta": th, "delta": de}
 
     # -- schedule (never changes results)
     def set_schedule(self, blocks: int = 0, tile_limit: int = 0) -> None:
-        check(lib().sco_set_schedule(self._h, int(blocks), int(tile_limit)), "sco_set_schedule")
+        check(lib().sco_set_schedule(self._h, int(blocks), int(tile_limit)), "sco_set_schedule", self._h)
 
     def schedule(self) -> tuple[int, int]:
         b, t = ctypes.c_int(), ctypes.c_int()
-        check(lib().sco_get_schedule(self._h, ctypes.byref(b), ctypes.byref(t)), "sco_get_schedule")
+        check(lib().sco_get_schedule(self._h, ctypes.byref(b), ctypes.byref(t)), "sco_get_schedule", self._h)
         return b.value, t.value
 
     def autotune(self, trial_steps: int = 3) -> dict:
         b, t, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
         check(lib().sco_autotune(self._h, int(trial_steps), ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)),
-              "sco_autotune")
+              "sco_autotune", self._h)
         return {"blocks": b.value, "tile_limit": t.value, "ms_per_step": ms.value}
 
     def phase_times(self) -> tuple[float, float, float]:
         out = (ctypes.c_float * 3)()
-        check(lib().sco_phase_times(self._h, out), "sco_phase_times")
+        check(lib().sco_phase_times(self._h, out), "sco_phase_times", self._h)
         return tuple(out)
 
     def trace(self, enable: bool = True) -> None:
-        check(lib().sco_trace(self._h, int(enable)), "sco_trace")
+        check(lib().sco_trace(self._h, int(enable)), "sco_trace", self._h)
 
     def trace_read(self) -> list[tuple[int, float]]:
         n = ctypes.c_int(0)
@@ -177,9 +177,9 @@ class SCO:
         us = np.zeros(256)
         check(lib().sco_trace_read(self._h, ids.ctypes.data_as(ctypes.c_void_p),
                                    us.ctypes.data_as(ctypes.c_void_p), 256, ctypes.byref(n)),
-              "sco_trace_read")
+              "sco_trace_read", self._h)
         k = min(n.value, 256)
         return list(zip(ids[:k].tolist(), us[:k].tolist()))
 
     def reset_counters(self) -> None:
-        check(lib().sco_reset_counters(self._h), "sco_reset_counters")
+        check(lib().sco_reset_counters(self._h), "sco_reset_counters", self._h)

@@ -195,7 +195,7 @@ struct sco_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float phase_ms[3] = {0, 0, 0};
   int64_t flags_seen = 0;
-  int last_err = 0;
+  uint32_t last_flags = 0;  // flags of the last flagged launch consumed
 };
 
 namespace {
@@ -226,14 +226,16 @@ int consume_flags(sco_ctx* c) {
   if (rc) return rc;
   if (f == 0) return SCO_OK;
   c->flags_seen |= f;
-  // a flagged launch may have stopped part-way: the bond graph and colouring are not
-  // valid any more (the device words are cleared with the rest of the sync block)
+  c->last_flags = f;
+  // a flagged launch stopped at a barrier and later launches did nothing: the bond
+  // graph and colouring are not valid any more (the device words are cleared with
+  // the rest of the sync block, the halt word included)
   c->graph_state = 0;
   HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, sizeof(SyncWords), c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  if (f & SCO_FLAG_TIMEOUT) return SCO_EINTERNAL;
-  if (f & SCO_FLAG_PALETTE) return SCO_EINTERNAL;
+  if (f & SCO_FLAG_TIMEOUT) return SCO_ETIMEOUT;
   if (f & SCO_FLAG_OVERFLOW) return SCO_EOVERFLOW;
+  if (f & SCO_FLAG_PALETTE) return SCO_EPALETTE;
   return SCO_EINTERNAL;
 }
 
@@ -269,8 +271,11 @@ const char* sco_strerror(int code) {
     case SCO_EINVAL: return "invalid argument";
     case SCO_EHIP: return "HIP runtime error";
     case SCO_EOVERFLOW: return "surviving bonds exceeded the edge capacity";
-    case SCO_EINTERNAL: return "internal invariant failed or device wait timed out";
+    case SCO_EINTERNAL: return "internal invariant failed (colouring or sweep without a valid bond graph, or "
+                                  "a CSR row out of range)";
     case SCO_ENOSPC: return "workspace too small";
+    case SCO_ETIMEOUT: return "a bounded device wait timed out (not every block of the persistent kernel ran)";
+    case SCO_EPALETTE: return "the union graph needs more than 255 colours";
     default: return "unknown error";
   }
 }
@@ -403,6 +408,9 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
     d.neg_beta32 = static_cast<float>(-beta);
     d.twoJ32 = static_cast<float>(d.twoJ);
     d.twoJ32_exact = static_cast<double>(d.twoJ32) == d.twoJ ? 1 : 0;
+    // an FP32 gap decision is at least inv_rate 2^-20 from the compared table value;
+    // it may stand only where no near tie (1e-12 relative) of the FP64 gap can hide
+    d.fp32_gap = d.inv_rate * 0x1p-20 > 2e-12 * d.C_top ? 1 : 0;
     for (int k = -4; k <= 4; ++k) {
       const double dE = (2.0 * p.J) * static_cast<double>(k);
       d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
@@ -548,6 +556,14 @@ int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
     if (rc) return rc;
     c->graph_state = 2;
   }
+  // a step that raised a flag ended at a barrier and every later launch did nothing
+  return n_steps > 0 ? consume_flags(c) : SCO_OK;
+}
+
+int sco_get_flags(sco_ctx* c, int64_t* last, int64_t* seen) {
+  if (!c) return SCO_EINVAL;
+  if (last) *last = c->last_flags;
+  if (seen) *seen = c->flags_seen;
   return SCO_OK;
 }
 
@@ -666,6 +682,7 @@ int sco_reset_counters(sco_ctx* c) {
   for (auto& s : st) s.accepted = s.attempts = s.rechecks = s.near_ties = 0;
   HIP_TRY(hipMemcpy(at<ChainState>(c, c->lay.off_st), st.data(), sizeof(ChainState) * c->n, hipMemcpyHostToDevice));
   c->flags_seen = 0;
+  c->last_flags = 0;
   return SCO_OK;
 }
 
@@ -719,6 +736,7 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
     o.attempts = static_cast<int64_t>(s.attempts);
     o.rechecks = static_cast<int64_t>(s.rechecks);
     o.flags = c->flags_seen;
+    o.near_ties = static_cast<int64_t>(s.near_ties);
   }
   return fr;
 }

@@ -40,6 +40,7 @@ struct ChainDesc {
   double pacc[9];          // exchange-only flips: index s_v * nn + 4; >= 1 means always accept
   float inv_rate32, neg_beta32, twoJ32;  // FP32 copies (precision 1)
   int32_t twoJ32_exact;                   // 2J is exact in FP32: bond-free fields are exact
+  int32_t fp32_gap;                       // precision 1 may decide switching gaps in FP32
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
 };
@@ -54,14 +55,18 @@ struct ChainState {
 };
 
 // Device-wide synchronisation words (each counter on its own 128-byte line).
+// gen, stop, top and grp are cleared together by the host (barrier counters).
 struct SyncWords {
-  uint32_t gen, pad0[31];
+  uint32_t gen, pad0[31];   // barrier instances completed since the counters were cleared
+  uint32_t stop, padS[31];  // generation of the last barrier that found a flag raised
   unsigned long long top, pad1[15];
   unsigned long long grp[SCO_BAR_GROUPS * 16];
-  uint32_t flags, qmax, mmax;
+  uint32_t flags;        // SCO_FLAG_* raised since the host last consumed them
+  uint32_t halt;         // 1 once a barrier ended a launch on a raised flag: later launches do nothing
+  uint32_t qmax, mmax;
   uint32_t graph_valid;  // 1 once a switching phase completed (0 while one runs)
   uint32_t color_valid;  // 1 once a colouring of the current graph completed
-  uint32_t pad2[27];
+  uint32_t pad2[26];
 };
 
 // Arguments of the persistent step kernel (all device pointers into the workspace).

@@ -98,6 +98,10 @@ __device__ __forceinline__ double unit52(uint32_t lo, uint32_t hi) {
 }
 
 // ------------------------------------------------------------------ helpers
+// |a - b| <= 1e-12 |b|: a decision this close may differ from a host evaluation whose
+// exp / log differ in the last bit; such decisions are counted (near ties).
+__device__ __forceinline__ bool near_tie(double a, double b) { return fabs(a - b) <= 1e-12 * fabs(b); }
+
 __device__ __forceinline__ int64_t gtid() {
   return static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
 }
@@ -136,12 +140,20 @@ __device__ __forceinline__ void st_relaxed(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Coherent read for polling: a read-modify-write at device scope is performed where
-// all XCDs see the same value, while a plain load (even device-scope) has been seen to
-// keep returning a stale line on one XCD.
+// Coherent read for polling: a read-modify-write at device scope is performed at the
+// one point where every XCD's atomics to the address are ordered, so it returns the
+// latest value in the address's modification order.  (A plain load, even an
+// agent-scope one, may be served from a line that this XCD's L2 still holds.)
 template <typename T>
 __device__ __forceinline__ T ld_poll(T* p) {
   return __hip_atomic_fetch_or(p, T(0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishing store for a word that other blocks poll: an atomic exchange, performed
+// at the same point as the polls' read-modify-writes (no returned value is waited for).
+template <typename T>
+__device__ __forceinline__ void st_publish(T* p, T v) {
+  (void)__hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void set_flag(SyncWords* s, uint32_t f) {
@@ -149,56 +161,105 @@ __device__ __forceinline__ void set_flag(SyncWords* s, uint32_t f) {
 }
 
 __device__ __forceinline__ bool timed_out(SyncWords* s) {
-  return (ld_relaxed(&s->flags) & SCO_FLAG_TIMEOUT) != 0;
+  return (ld_poll(&s->flags) & SCO_FLAG_TIMEOUT) != 0;
 }
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // ~ seconds; reached only if residency fails
 
-// Device-wide barrier (all blocks resident).  Arrival is counted in SCO_BAR_GROUPS
-// groups, then by group; counters only grow, so nothing is reset between barriers.
-// One wave per block fences: a release before arriving and an acquire after the
-// generation word moved, which makes every write of the block before the barrier
-// visible to every read after it.  Returns false once a wait has timed out.
+// Device-wide barriers (all blocks resident).  Arrival is counted in SCO_BAR_GROUPS
+// groups, then by group, on counters that only grow between host resets (the host
+// clears gen, stop, top and grp together).  A block's ticket a in its group (members
+// blocks arrive there per barrier) names the barrier instance b = (a - 1) / members,
+// counted from the reset; the block that completes the last group publishes the
+// generation b + 1, and every other block waits until gen has reached b + 1.  No
+// block reads gen before it arrives, so neither a stale copy of gen nor a load
+// performed after the arrival can make it wait for the wrong generation.  Every
+// access to gen, stop and the counters is a device-scope read-modify-write, so all
+// of them are ordered at one point per word.
+//
+// `full`: the release/acquire sequence of the documented agent-scope memory model
+// carries every write before the barrier to every read after it:
+//   member   fence release; arrival RMW on its group counter
+//   group completer: fence acq_rel after its group RMW (acquires its members'
+//            release sequences, releases them on), then the RMW on the top counter
+//   last arriver: fence acq_rel after the top RMW, then the exchange that publishes
+//   waiter   RMW polls of gen until it reaches the target; fence acquire
+// (fences at agent scope: L2 write-back / invalidation on each XCD).  The last
+// arriver also copies the verdict of the raised flags into `stop`, so that every block
+// takes the same decision to end the launch at the same barrier.
+//
+// Without `full` (colour classes of a sweep) only the control is ordered; the data
+// the classes exchange (spins) is written and read with agent-scope atomics and the
+// barrier adds no cache maintenance.
+struct BarTicket {
+  uint32_t target;
+  bool last;
+};
+
+__device__ __forceinline__ BarTicket bar_arrive(SyncWords* s, bool full) {
+  const uint32_t nb = gridDim.x;
+  const uint32_t ng = nb < SCO_BAR_GROUPS ? nb : SCO_BAR_GROUPS;
+  const uint32_t grp = blockIdx.x % ng;
+  const uint32_t members = nb / ng + (grp < nb % ng ? 1u : 0u);
+  const unsigned long long a =
+      __hip_atomic_fetch_add(&s->grp[grp * 16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+  const unsigned long long b = (a - 1ull) / members;
+  BarTicket t{static_cast<uint32_t>(b + 1ull), false};
+  if (a % members == 0) {  // this block completes its group for instance b
+    if (full) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    const unsigned long long k =
+        __hip_atomic_fetch_add(&s->top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+    t.last = (k % ng == 0);
+  }
+  return t;
+}
+
+// Waits for generation `target`; false once a wait has timed out.
+__device__ __forceinline__ bool bar_wait(SyncWords* s, uint32_t target) {
+  uint32_t n = 0;
+  while (static_cast<int32_t>(ld_poll(&s->gen) - target) < 0) {
+    if ((n & 63u) == 63u && timed_out(s)) return false;
+    if (++n > kSpinLimit) {
+      set_flag(s, SCO_FLAG_TIMEOUT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Full device-wide barrier between dependent phases.  Returns false when the launch
+// must end: a wait timed out, or a flag (edge overflow, palette, state) was raised
+// before the barrier; every block then returns false at the same barrier.
 __device__ __forceinline__ bool grid_barrier(SyncWords* s) {
   __shared__ uint32_t s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t nb = gridDim.x;
-    const uint32_t ng = nb < SCO_BAR_GROUPS ? nb : SCO_BAR_GROUPS;
-    const uint32_t grp = blockIdx.x % ng;
-    const uint32_t members = nb / ng + (grp < nb % ng ? 1u : 0u);
-    const uint32_t gen = ld_relaxed(&s->gen);
-    bool last = false;
-    const unsigned long long a =
-        __hip_atomic_fetch_add(&s->grp[grp * 16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-    if (a % members == 0) {
-      const unsigned long long t =
-          __hip_atomic_fetch_add(&s->top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-      last = (t % ng == 0);
-    }
-    if (last) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(&s->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint32_t n = 0;
-      while (ld_poll(&s->gen) == gen) {
-        if (timed_out(s)) break;
-        if (++n > kSpinLimit) {
-          set_flag(s, SCO_FLAG_TIMEOUT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    const BarTicket t = bar_arrive(s, true);
+    bool ok = true;
+    if (t.last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (ld_poll(&s->flags) != 0) {
+        st_publish(&s->stop, t.target);
+        st_publish(&s->halt, 1u);
       }
+      st_publish(&s->gen, t.target);
+    } else {
+      ok = bar_wait(s, t.target);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_ok = timed_out(s) ? 0u : 1u;
+    // stop is written only by last arrivers; the next one can write it only after
+    // this block has arrived at the next barrier, so this read sees this barrier's
+    // verdict
+    if (ok && ld_poll(&s->stop) == t.target) ok = false;
+    s_ok = ok ? 1u : 0u;
   }
   __syncthreads();
   return s_ok != 0;
 }
 
-// Device-wide barrier between the colour classes of one phase, for data that is
+// Device-wide barrier between the colour classes of one sweep phase, for data that is
 // written and read only with device-coherent (agent-scope) accesses: every wave waits
 // until its own stores have completed, then the same arrival and bounded wait as
 // grid_barrier, without the L2 write-back and invalidation of the agent-scope fences,
@@ -208,40 +269,19 @@ __device__ __forceinline__ bool grid_barrier(SyncWords* s) {
 // valid in that XCD's L2, and its later coherent loads are served from there.  So
 // between two full barriers every coherently written word must be written by blocks of
 // one XCD only (here: by the one block that owns the site for the whole phase), or a
-// former writer reads its own stale copy.  The KW levels rebalance sites between
-// levels, so each level ends with a full barrier; so does the tile phase.
+// former writer reads its own stale copy.  The barrier words themselves are written
+// by whichever block arrives last; they are therefore touched only by
+// read-modify-writes, which this rule does not concern.
 __device__ __forceinline__ bool class_barrier(SyncWords* s) {
   __shared__ uint32_t s_ok;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t nb = gridDim.x;
-    const uint32_t ng = nb < SCO_BAR_GROUPS ? nb : SCO_BAR_GROUPS;
-    const uint32_t grp = blockIdx.x % ng;
-    const uint32_t members = nb / ng + (grp < nb % ng ? 1u : 0u);
-    const uint32_t gen = ld_relaxed(&s->gen);
-    bool last = false;
-    const unsigned long long a =
-        __hip_atomic_fetch_add(&s->grp[grp * 16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-    if (a % members == 0) {
-      const unsigned long long t =
-          __hip_atomic_fetch_add(&s->top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-      last = (t % ng == 0);
-    }
-    if (last) {
-      st_relaxed(&s->gen, gen + 1u);
-    } else {
-      uint32_t n = 0;
-      while (ld_poll(&s->gen) == gen) {
-        if (timed_out(s)) break;
-        if (++n > kSpinLimit) {
-          set_flag(s, SCO_FLAG_TIMEOUT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    s_ok = timed_out(s) ? 0u : 1u;
+    const BarTicket t = bar_arrive(s, false);
+    bool ok = true;
+    if (t.last) st_publish(&s->gen, t.target);
+    else ok = bar_wait(s, t.target);
+    s_ok = ok ? 1u : 0u;
   }
   __syncthreads();
   return s_ok != 0;
@@ -395,6 +435,32 @@ struct ColorSet64 {
   __device__ __forceinline__ void add_if(bool on, int c) { w |= on ? 1ull << (c & 63) : 0ull; }
   __device__ __forceinline__ int first_free() const {
     return ~w ? __ffsll(static_cast<unsigned long long>(~w)) - 1 : 64;
+  }
+};
+
+// Rare-event counts of a phase (FP32 decisions recomputed in FP64, near ties): kept
+// per thread for the first chain c0 of the block's range and added to its chain state
+// once per block by flush (every thread calls it); other chains take one device atomic
+// per event.
+struct Tally {
+  int c0;
+  uint32_t rechecks = 0u, ties = 0u;
+  __device__ __forceinline__ explicit Tally(int first) : c0(first) {}
+  __device__ __forceinline__ void recheck(const StepArgs& a, int c) {
+    if (c == c0) ++rechecks;
+    else atomicAdd(&a.st[c].rechecks, 1ull);
+  }
+  __device__ __forceinline__ void tie(const StepArgs& a, int c) {
+    if (c == c0) ++ties;
+    else atomicAdd(&a.st[c].near_ties, 1ull);
+  }
+  __device__ __forceinline__ void flush(const StepArgs& a) {
+    const unsigned long long r = block_sum(static_cast<unsigned long long>(rechecks));
+    const unsigned long long t = block_sum(static_cast<unsigned long long>(ties));
+    if (threadIdx.x == 0 && c0 < a.n_chains) {
+      if (r) atomicAdd(&a.st[c0].rechecks, r);
+      if (t) atomicAdd(&a.st[c0].near_ties, t);
+    }
   }
 };
 
@@ -586,7 +652,8 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTabl
 // then the gap is recomputed in FP64 (counted in `rechecks`).
 template <class Desc>
 __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& desc_of, const SwitchTables& tb,
-                                                uint32_t step, Owner& o, int& j, int& m, uint32_t& kc) {
+                                                uint32_t step, Owner& o, int& j, int& m, uint32_t& kc,
+                                                Tally& tally) {
   const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -606,10 +673,12 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
   }
   const double u1 = unit52(wlo, whi);
   bool done = false;
-  if (d.precision == 1) {
+  if (d.precision == 1 && d.fp32_gap) {
     // -log u rounded through FP32 (u to float: 2^-24 relative; logf: about one ulp;
     // the product: two roundings) stays within inv_rate (2^-24 + 2^-22 E) of the exact
-    // gap; tol takes four times that, plus the rounding of the FP64 sums.
+    // gap; tol takes four times that, plus the rounding of the FP64 sums.  fp32_gap
+    // holds when inv_rate 2^-20 > 2e-12 C_top: a decision taken here is then far from
+    // any near tie of the FP64 evaluation.
     const float E = -logf(static_cast<float>(u1));
     const double target = o.Cpos + static_cast<double>(E * d.inv_rate32);
     const double tol = static_cast<double>(d.inv_rate32) * (static_cast<double>(E) + 1.0) * 0x1p-20 + target * 0x1p-50;
@@ -621,15 +690,18 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
       m = table_search(d, tb, target, o.pos);
       done = tb.c_at(d, m) >= target + tol && (m == o.pos + 1 || tb.c_at(d, m - 1) < target - tol);
     }
-    if (!done) atomicAdd(&a.st[o.c].rechecks, 1ull);  // rare: one atomic each
+    if (!done) tally.recheck(a, o.c);
   }
   if (!done) {
     const double target = o.Cpos + (-log(u1)) * d.inv_rate;
+    if (near_tie(target, d.C_top)) tally.tie(a, o.c);
     if (target > d.C_top) {
       o.live = false;
       return false;
     }
     m = table_search(d, tb, target, o.pos);
+    if (near_tie(target, tb.c_at(d, m)) || (m - 1 > o.pos && near_tie(target, tb.c_at(d, m - 1))))
+      tally.tie(a, o.c);
   }
   const uint32_t p = tb.hd_at(d, m);
   const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
@@ -700,6 +772,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     }
     return ns;
   };
+  Tally tally(ch0 < ch1 ? a.chunk_chain[ch0] : 0);
   auto run = [&](const auto& desc_of, const SwitchTables& tb, int c_uni) {
     bool pool = true;
     Owner O[kOwners];
@@ -725,7 +798,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         jc[u] = -1;
         mc[u] = 0;
         kc[u] = 0;
-        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u]);
+        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally);
       }
 #pragma unroll
       for (int u = 0; u < kOwners; ++u)
@@ -782,7 +855,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
   }
   if (threadIdx.x == 0)
     for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? ne : 0u;
-  __syncthreads();
+  tally.flush(a);  // its block sums also order the block's work before the return
 }
 
 // ------------------------------------------------------------------ prefix sum
@@ -1764,6 +1837,10 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
               g = vb + v;
               const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
               nn_sites(x, y, K.L, K.periodic, nbs);
+              // a first read may return an older value of a word (a copy this XCD's L2
+              // still holds): an older value shows a higher-class neighbour as
+              // undecided, so the site only waits and re-reads with read-modify-writes;
+              // a word decided at this level does not change again within it
 #pragma unroll
               for (int t = 0; t < 4; ++t) wn[t] = nbs[t] >= 0 ? ld_relaxed(&a.kw_word[vb + nbs[t]]) : 0u;
               rb = a.row_ptr[g];
@@ -1823,7 +1900,8 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
               set_flag(a.sync, SCO_FLAG_PALETTE);
               nc = q - 1;
             }
-            st_relaxed(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
+            // published where the waiting neighbours' read-modify-write polls read
+            st_publish(&a.kw_word[g], (static_cast<uint32_t>(p) << 18) | (static_cast<uint32_t>(rmax + 1) << 9) |
                                           static_cast<uint32_t>(nc));
             if (c != cloc) {
               if (cloc >= 0) atomicMax(&brounds[cloc], rloc);
@@ -1892,6 +1970,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   const int c_lo = r0 < r1 ? a.chunk_chain[r0 >> SCO_CHUNK_SHIFT] : 0;
   const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
   const bool local_cd = c_hi - c_lo < kLocalChains;
+  Tally tally(c_lo);
   if (local_cd)
     for (int i = tid; i <= c_hi - c_lo; i += kBlock) lcd[i] = a.cd[c_lo + i];
   for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
@@ -2122,7 +2201,9 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 } else {
                   const W4 w = philox10_wide(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
                                         d.seed, d.chain_id);
-                  acc[r] = unit52(w.x, w.y) < pa;
+                  const double u = unit52(w.x, w.y);
+                  if (fabs(u - pa) < 1e-12) tally.tie(a, c);
+                  acc[r] = u < pa;
                 }
               }
             } else {
@@ -2157,12 +2238,13 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                   const double errP =
                       static_cast<double>(pr) * (static_cast<double>(-d.neg_beta32) * errE * 1.01 + fabs(x) * 0x1p-21 + 0x1p-21) +
                       0x1p-126;
-                  if (fabs(u - static_cast<double>(pr)) > errP) {
+                  // beyond errP + 1e-12 the FP64 decision is the same and no near tie
+                  if (fabs(u - static_cast<double>(pr)) > errP + 1e-12) {
                     acc[r] = u < static_cast<double>(pr);
                     done = true;
                   }
                 }
-                if (!done) atomicAdd(&a.st[c].rechecks, 1ull);
+                if (!done) tally.recheck(a, c);
               }
               if (!done) {
                 double h = d.twoJ * static_cast<double>(nsum[r]);
@@ -2178,7 +2260,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                                         d.seed, d.chain_id);
                   const double u = unit52(w.x, w.y);
                   const double pr = exp(d.neg_beta * dE);
-                  if (fabs(u - pr) < 1e-12) atomicAdd(&a.st[c].near_ties, 1ull);
+                  if (fabs(u - pr) < 1e-12) tally.tie(a, c);
                   acc[r] = u < pr;
                 }
               }
@@ -2225,6 +2307,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   else if (local_cd && r1 - r0 <= kListCap) ok = body(lds_list, ldesc, Flag<false>{});
   else ok = body(lst_mem, [&](int c) -> const ChainDesc& { return a.cd[c]; }, Flag<false>{});
   if (!ok) return false;
+  tally.flush(a);
   for (int c = tid; c < a.n_chains; c += kBlock)
     if (bacc[c]) atomicAdd(&a.st[c].accepted, bacc[c]);
   if (blockIdx.x == 0)
@@ -2245,6 +2328,17 @@ template <uint32_t phases>
 __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, PhaseLds& lds, KwShared& ks) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  {
+    // A launch after one that ended on a raised flag does nothing until the host has
+    // consumed the flags: the spins stay as the failed step found them.  halt is
+    // written only by the last arriver of a barrier, which every block of this launch
+    // reaches after this check; a timeout needs seconds of waiting inside a launch.
+    __shared__ uint32_t s_halt;
+    if (threadIdx.x == 0)
+      s_halt = (ld_poll(&a.sync->halt) != 0 || (ld_poll(&a.sync->flags) & SCO_FLAG_TIMEOUT) != 0) ? 1u : 0u;
+    __syncthreads();
+    if (s_halt != 0) return false;
+  }
   if constexpr ((phases & PH_SWITCH) != 0) {
     // the degree and cursor arrays start from zero whatever an earlier launch left
     if (lead) {

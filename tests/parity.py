@@ -64,8 +64,7 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
         t = first_step + s
         gpu.step(t)
         before = [r.observables(dipolar="none")["near_ties"] for r in refs]
-        for r in refs:
-            r.step(t)
+        step_all(refs, t)
         graph = graph_every > 0 and (s % graph_every == 0 or s == n_steps - 1)
         for c, r in enumerate(refs):
             diffs = compare_state(gpu, r, c, f"step {t}", graph=graph)
@@ -73,22 +72,40 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
                 ties = r.observables(dipolar="none")["near_ties"] - before[c]
                 if ties == 0:
                     raise AssertionError(f"chain {c} step {t}: {diffs} differ with no near tie "
-                                         f"(params {params[c]})")
+                                         f"in that step (params {params[c]})")
+                log(f"  chain {c} step {t}: {diffs} differ after {ties} near tie(s); resynchronised")
                 tolerated += 1
                 r.spins = gpu.spins(c)
         if obs_every and (s % obs_every == 0 or s == n_steps - 1):
-            compare_observables(gpu, refs)
+            compare_observables(gpu, refs, ties=tolerated == 0)
     out = {"tolerated": tolerated, "gpu": gpu, "refs": refs}
     return out
 
 
-def compare_observables(gpu, refs) -> None:
+def step_all(refs, t: int) -> None:
+    """One step of every oracle chain; several chains run on host threads (each call
+    into the C oracle releases the interpreter lock)."""
+    if len(refs) == 1:
+        refs[0].step(t)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=min(len(refs), 16)) as ex:
+        list(ex.map(lambda r: r.step(t), refs))
+
+
+def compare_observables(gpu, refs, ties: bool = True) -> None:
+    """Integer observables identical, energies within 1e-12 relative; with `ties`, the
+    GPU's count of near-tie decisions equals the oracle's (both count the same
+    comparisons; only a run that was resynchronised after a tie may differ)."""
     go = gpu.observables()
     for c, r in enumerate(refs):
         ro = r.observables()
         g = go[c]
         for k in ("M", "n_edges", "delta_union", "q", "colors_used", "kw_levels", "kw_rounds"):
             assert g[k] == ro[k], (c, k, g[k], ro[k])
+        if ties:
+            assert g["near_ties"] == ro["near_ties"], (c, g["near_ties"], ro["near_ties"])
         assert g["E_exchange"] == ro["E_exchange"]
         assert abs(g["E_dipolar"] - ro["E_dipolar"]) <= 1e-12 * max(1.0, abs(ro["E_dipolar"])), (
             c, g["E_dipolar"], ro["E_dipolar"])

@@ -110,18 +110,34 @@ def test_checkpoint_resume_exact():
     np.testing.assert_array_equal(a.spins(0), b.spins(0))
 
 
-def test_edge_capacity_overflow_is_reported():
+def test_edge_capacity_overflow_stops_the_step():
+    """An edge overflow ends the launch at the barrier after the switching: no spin
+    moves, the later launches do nothing, and the next synchronising call reports it
+    (with the flag named); the context stays usable afterwards."""
     from paper_1503_03295_amd import SCO, ScoError
 
     p = workloads.chain(64, True, 0.8, 3.0)
     p["edge_factor"] = 1
     g = SCO([gpu_params(p)], device="cuda:0")
+    s0 = g.spins(0)
     g.step(0)
+    g.step(1)
+    np.testing.assert_array_equal(g.spins(0), s0)
     with pytest.raises(ScoError) as e:
         g.observables()
+    assert e.value.code == -3 and e.value.flags == 1, e.value
+    np.testing.assert_array_equal(g.spins(0), s0)
+    assert g.observables()[0]["attempts"] == 0
+    # sco_run reports the flag of its own steps
+    with pytest.raises(ScoError) as e:
+        g.run(0, 3)
     assert e.value.code == -3
-    # the context stays usable after the flag was consumed
-    g.observables()
+    np.testing.assert_array_equal(g.spins(0), s0)
+    # a chain with room runs on
+    q = dict(p, edge_factor=16)
+    h = SCO([gpu_params(q)], device="cuda:0")
+    h.run(0, 3)
+    assert h.observables()[0]["attempts"] == 3 * 64 * 64
 
 
 def test_large_lattice_first_steps():
