@@ -381,10 +381,17 @@ static int union_neighbours(const orc_chain* c, int v, int32_t* out, int cap) {
 int orc_color(orc_chain* c) {
   int N = c->N, maxdeg = 0;
   int32_t nbuf[4096];
+  /* the union graph's adjacency, listed once per colouring */
+  int32_t* uoff = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N + 1));
+  size_t ucap = (size_t)N * 4 + 2 * (size_t)c->n_edges + 1, un = 0;
+  int32_t* uadj = (int32_t*)malloc(sizeof(int32_t) * ucap);
   for (int v = 0; v < N; ++v) {
     int d = union_neighbours(c, v, nbuf, 4096);
     if (d > maxdeg) maxdeg = d;
+    uoff[v] = (int32_t)un;
+    for (int a = 0; a < d; ++a) uadj[un++] = nbuf[a];
   }
+  uoff[N] = (int32_t)un;
   int q = maxdeg + 1;
   c->delta_union = maxdeg;
   c->q = q;
@@ -394,30 +401,32 @@ int orc_color(orc_chain* c) {
   c->kw_rounds = 0;
   memset(c->kw_rounds_level, 0, 64 * sizeof(int32_t));
   int32_t* cur = c->color;
-  int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
-  uint8_t* pend = (uint8_t*)malloc((size_t)N);
-  uint8_t* npend = (uint8_t*)malloc((size_t)N);
+  uint8_t* pend = (uint8_t*)calloc((size_t)N, 1);
+  int32_t* plist = (int32_t*)malloc(sizeof(int32_t) * (size_t)N); /* pending vertices */
+  int32_t* dec_v = (int32_t*)malloc(sizeof(int32_t) * (size_t)N); /* decisions of a round */
+  int32_t* dec_c = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
   uint8_t* used = (uint8_t*)malloc((size_t)q);
+  int fail = 0;
   for (int v = 0; v < N; ++v) cur[v] = v % q;
-  for (int p = 1; p <= M; ++p) {
+  for (int p = 1; p <= M && !fail; ++p) {
     int npending = 0;
     for (int v = 0; v < N; ++v) {
       pend[v] = (uint8_t)(((v / q) >> (p - 1)) & 1);
-      if (pend[v]) { cur[v] += q; ++npending; }
+      if (pend[v]) { cur[v] += q; plist[npending++] = v; }
     }
     int rounds = 0;
     while (npending > 0) {
       ++rounds;
-      memcpy(nxt, cur, sizeof(int32_t) * (size_t)N);
-      memcpy(npend, pend, (size_t)N);
-      for (int v = 0; v < N; ++v) {
-        if (!pend[v]) continue;
+      /* every decision of the round reads the colours and pending marks left by the
+       * previous round; they are applied together afterwards */
+      int ndec = 0;
+      for (int k = 0; k < npending; ++k) {
+        int v = plist[k];
         int grp = (v / q) >> p;
-        int d = union_neighbours(c, v, nbuf, 4096);
         int localmax = 1;
         memset(used, 0, (size_t)q);
-        for (int a = 0; a < d; ++a) {
-          int u = nbuf[a];
+        for (int x = uoff[v]; x < uoff[v + 1]; ++x) {
+          int u = uadj[x];
           if (((u / q) >> p) != grp) continue;
           if (pend[u] && cur[u] > cur[v]) localmax = 0;
           if (cur[u] < q) used[cur[u]] = 1;
@@ -425,19 +434,26 @@ int orc_color(orc_chain* c) {
         if (!localmax) continue;
         int nc = 0;
         while (nc < q && used[nc]) ++nc;
-        if (nc == q) { free(nxt); free(pend); free(npend); free(used); return -1; }
-        nxt[v] = nc;
-        npend[v] = 0;
-        --npending;
+        if (nc == q) { fail = 1; break; }
+        dec_v[ndec] = v;
+        dec_c[ndec] = nc;
+        ++ndec;
       }
-      memcpy(cur, nxt, sizeof(int32_t) * (size_t)N);
-      memcpy(pend, npend, (size_t)N);
+      if (fail) break;
+      for (int k = 0; k < ndec; ++k) {
+        cur[dec_v[k]] = dec_c[k];
+        pend[dec_v[k]] = 0;
+      }
+      int keep = 0;
+      for (int k = 0; k < npending; ++k)
+        if (pend[plist[k]]) plist[keep++] = plist[k];
+      npending = keep;
     }
     c->kw_rounds_level[p < 64 ? p : 63] = rounds;
     c->kw_rounds += rounds;
   }
-  free(nxt); free(pend); free(npend); free(used);
-  return 0;
+  free(uoff); free(uadj); free(pend); free(plist); free(dec_v); free(dec_c); free(used);
+  return fail ? -1 : 0;
 }
 
 /* ------------------------------------------------- step (B): Metropolis on H'
