@@ -70,7 +70,7 @@ typedef struct {
   uint32_t seed;      /* Philox key word 0 */
   uint32_t chain_id;  /* Philox key word 1 */
   int32_t precision;  /* 0: FP64 decisions; 1: FP32 accumulation + FP64 recheck (same chain) */
-  int32_t edge_factor;/* directed-bond capacity per site (0: default 4) */
+  int32_t edge_factor;/* directed-bond capacity per site, 0 .. 256 (0: default 4) */
 } sco_chain_params;
 
 /* Per-chain observables and counters, FP64 / exact integers. */
@@ -135,8 +135,16 @@ int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
  * synchronising call consumed, and all flags seen since the last counter reset. */
 int sco_get_flags(sco_ctx* ctx, int64_t* last, int64_t* seen);
 
-/* Observables of every chain into host_out[n_chains]; synchronises. */
+/* Observables of every chain into host_out[n_chains]; synchronises.  E_exchange and M
+ * follow Eq. (6) restricted to perpendicular spins; E_dipolar = sum_m J_m C_m with the
+ * exact integer pair correlation C_m of each half-displacement (O(N K / 32) bit
+ * operations); n_edges, delta_union, q and the colours are the graph statistics of
+ * Sec. 3.2 (mean degree 2 n_edges / N) for the last switching and colouring. */
 int sco_observables(sco_ctx* ctx, sco_obs* host_out);
+
+/* The same without the dipolar energy (E and E_dipolar are NaN): integer observables,
+ * graph statistics and counters only, in O(N).  Synchronises. */
+int sco_counters(sco_ctx* ctx, sco_obs* host_out);
 
 /* Checkpoint / resume: spins of one chain (N int8 values) to / from host memory. */
 int sco_get_spins(sco_ctx* ctx, int chain, int8_t* host_out);

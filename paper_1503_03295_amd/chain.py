@@ -109,6 +109,12 @@ class SCO:
         check(lib().sco_observables(self._h, out), "sco_observables", self._h)
         return [o.as_dict() for o in out]
 
+    def counters(self) -> list[dict]:
+        """Observables without the dipolar energy (E, E_dipolar NaN), O(N)."""
+        out = (ObsC * self.n_chains)()
+        check(lib().sco_counters(self._h, out), "sco_counters", self._h)
+        return [o.as_dict() for o in out]
+
     def spins(self, chain: int = 0) -> np.ndarray:
         p = self.params[chain]
         out = np.empty(p.L * p.L, np.int8)

@@ -33,7 +33,7 @@ bool valid(const sco_chain_params& p) {
   if (!std::isfinite(p.T) || !std::isfinite(p.kappa) || !std::isfinite(p.J) || !std::isfinite(p.D)) return false;
   if (p.n_sw < 0 || p.n_images < 0 || p.n_images > 64) return false;
   if (p.precision != 0 && p.precision != 1) return false;
-  if (p.edge_factor < 0 || p.edge_factor > 64) return false;
+  if (p.edge_factor < 0 || p.edge_factor > 256) return false;
   return true;
 }
 
@@ -686,7 +686,8 @@ int sco_reset_counters(sco_ctx* c) {
   return SCO_OK;
 }
 
-int sco_observables(sco_ctx* c, sco_obs* out) {
+namespace {
+int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   if (!c || !out) return SCO_EINVAL;
   const int fr = consume_flags(c);
   const Layout& L = c->lay;
@@ -696,13 +697,11 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   HIP_TRY(hipMemsetAsync(d_used, 0, sizeof(uint32_t) * SCO_QWORDS * c->n, c->stream));
   HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
                              at<int8_t>(c, L.off_spin), at<uint16_t>(c, L.off_color), d_obs, d_used, L.G));
-  for (int ci = 0; ci < c->n; ++ci) {
+  for (int ci = 0; ci < c->n && dipolar; ++ci) {
     const ChainDesc& d = c->cd[ci];
-    const int t = L.chain_table[ci];
     HIP_TRY(sco_dev::obs_dipolar(c->stream, d.hd, d.J, d.K, d.L, d.periodic, at<int8_t>(c, L.off_spin), d.vbase,
                                  at<uint32_t>(c, L.off_bits), at<double>(c, L.off_prod), at<double>(c, L.off_dpart),
                                  at<double>(c, L.off_dres) + ci));
-    (void)t;
   }
   std::vector<ChainState> st(c->n);
   std::vector<unsigned long long> sums(2 * c->n);
@@ -712,8 +711,11 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(sums.data(), d_obs, sizeof(unsigned long long) * 2 * c->n, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(edip.data(), at<double>(c, L.off_dres), sizeof(double) * c->n, hipMemcpyDeviceToHost,
-                         c->stream));
+  if (dipolar)
+    HIP_TRY(hipMemcpyAsync(edip.data(), at<double>(c, L.off_dres), sizeof(double) * c->n, hipMemcpyDeviceToHost,
+                           c->stream));
+  else
+    std::fill(edip.begin(), edip.end(), std::nan(""));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int ci = 0; ci < c->n; ++ci) {
     sco_obs& o = out[ci];
@@ -740,6 +742,11 @@ int sco_observables(sco_ctx* c, sco_obs* out) {
   }
   return fr;
 }
+}  // namespace
+
+int sco_observables(sco_ctx* c, sco_obs* out) { return observables_impl(c, out, true); }
+
+int sco_counters(sco_ctx* c, sco_obs* out) { return observables_impl(c, out, false); }
 
 int sco_get_spins(sco_ctx* c, int chain, int8_t* host_out) {
   if (!c || chain < 0 || chain >= c->n || !host_out) return SCO_EINVAL;

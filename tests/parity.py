@@ -51,11 +51,15 @@ def compare_state(gpu, ref: oracle.OracleChain, chain: int, what: str, graph: bo
 
 
 def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_step: int = 0,
-               obs_every: int = 0) -> dict:
-    """Runs all chains in one GPU context and one oracle chain each; returns counts."""
+               obs_every: int = 0, schedule: tuple | None = None, counters_every: int = 0) -> dict:
+    """Runs all chains in one GPU context and one oracle chain each; returns counts.
+    obs_every: every observable (dipolar energy included); counters_every: the integer
+    observables only; schedule: (blocks, tile_limit) of the GPU context."""
     from paper_1503_03295_amd import SCO
 
     gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
+    if schedule is not None:
+        gpu.set_schedule(*schedule)
     refs = [oracle.OracleChain(oracle_params(p)) for p in params]
     tolerated = 0
     for c, r in enumerate(refs):
@@ -78,6 +82,8 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
                 r.spins = gpu.spins(c)
         if obs_every and (s % obs_every == 0 or s == n_steps - 1):
             compare_observables(gpu, refs, ties=tolerated == 0)
+        elif counters_every and (s % counters_every == 0 or s == n_steps - 1):
+            compare_observables(gpu, refs, ties=tolerated == 0, dipolar=False)
     out = {"tolerated": tolerated, "gpu": gpu, "refs": refs}
     return out
 
@@ -94,19 +100,21 @@ def step_all(refs, t: int) -> None:
         list(ex.map(lambda r: r.step(t), refs))
 
 
-def compare_observables(gpu, refs, ties: bool = True) -> None:
+def compare_observables(gpu, refs, ties: bool = True, dipolar: bool = True) -> None:
     """Integer observables identical, energies within 1e-12 relative; with `ties`, the
     GPU's count of near-tie decisions equals the oracle's (both count the same
     comparisons; only a run that was resynchronised after a tie may differ)."""
-    go = gpu.observables()
+    go = gpu.observables() if dipolar else gpu.counters()
     for c, r in enumerate(refs):
-        ro = r.observables()
+        ro = r.observables(dipolar="auto" if dipolar else "none")
         g = go[c]
         for k in ("M", "n_edges", "delta_union", "q", "colors_used", "kw_levels", "kw_rounds"):
             assert g[k] == ro[k], (c, k, g[k], ro[k])
         if ties:
             assert g["near_ties"] == ro["near_ties"], (c, g["near_ties"], ro["near_ties"])
         assert g["E_exchange"] == ro["E_exchange"]
+        if not dipolar:
+            continue
         assert abs(g["E_dipolar"] - ro["E_dipolar"]) <= 1e-12 * max(1.0, abs(ro["E_dipolar"])), (
             c, g["E_dipolar"], ro["E_dipolar"])
         assert abs(g["E"] - ro["E"]) <= 1e-12 * max(1.0, abs(ro["E"]))
