@@ -131,6 +131,26 @@ int sco_step(sco_ctx* ctx, uint64_t step);
  * before the failed step). */
 int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): sco_init + sco_run + sco_get_spins
+ * (+ sco_observables) of n_chains chains in one call that allocates nothing.  Their
+ * whole workspace lives in a static device array of the library, 64 MiB per GPU
+ * (held from the library's first use on that GPU until the process ends), so
+ * sco_workspace_size(params) must be at most 64 MiB (L up to about 512 periodic),
+ * else SCO_ENOSPC and nothing runs.
+ *   dev_spins_in   int8 +-1, the chains' sites concatenated in chain order (row-major,
+ *                  no padding); NULL draws the initial spins from Philox
+ *   dev_spins_out  the spins after steps first_step .. first_step + n_steps - 1, same
+ *                  layout (may equal dev_spins_in)
+ *   host_obs       NULL, or n_chains observables after the steps
+ * Returns SCO_OK or an error code as sco_init / sco_run; synchronises `stream`.  Every
+ * call on one GPU uses that GPU's one array and re-initialises it: calls that overlap
+ * on one GPU (other host threads, other streams) race and must be serialised by the
+ * caller. */
+int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* dev_spins_in,
+                    int8_t* dev_spins_out, uint64_t first_step, int n_steps, sco_obs* host_obs,
+                    void* stream);
+
 /* Device flags (SCO_FLAG bits as in sco_obs.flags) of the last flagged launch that a
  * synchronising call consumed, and all flags seen since the last counter reset. */
 int sco_get_flags(sco_ctx* ctx, int64_t* last, int64_t* seen);

@@ -45,6 +45,21 @@ def workspace_size(params: list[ChainParams]) -> int:
     return int(n.value)
 
 
+def run_noalloc(params: list[ChainParams], spins_in: torch.Tensor | None, spins_out: torch.Tensor,
+                first_step: int, n_steps: int, stream: torch.cuda.Stream | None = None,
+                observables: bool = True) -> list[dict] | None:
+    """sco_run_noalloc: n_steps steps of the chains with the library's static scratch
+    as workspace (no device allocation).  spins_in / spins_out: int8 device tensors of
+    the chains' sites concatenated (spins_in None: Philox start)."""
+    carr = (ChainParamsC * len(params))(*[p.to_c() for p in params])
+    st = stream if stream is not None else torch.cuda.current_stream(spins_out.device)
+    obs = (ObsC * len(params))() if observables else None
+    ip = ctypes.c_void_p(spins_in.data_ptr()) if spins_in is not None else None
+    check(lib().sco_run_noalloc(carr, len(params), ip, ctypes.c_void_p(spins_out.data_ptr()), first_step,
+                                n_steps, obs, ctypes.c_void_p(st.cuda_stream)), "sco_run_noalloc")
+    return [o.as_dict() for o in obs] if observables else None
+
+
 class SCO:
     """A batch of independent SCO chains resident on one GPU."""
 

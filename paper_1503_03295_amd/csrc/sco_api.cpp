@@ -196,6 +196,7 @@ struct sco_ctx {
   float phase_ms[3] = {0, 0, 0};
   int64_t flags_seen = 0;
   uint32_t last_flags = 0;  // flags of the last flagged launch consumed
+  uint32_t flags_host = 0;  // read-back word when there is no pinned staging
 };
 
 namespace {
@@ -212,9 +213,11 @@ T* at(sco_ctx* c, size_t off) {
 
 int read_flags(sco_ctx* c, uint32_t* flags) {
   const SyncWords* d = at<SyncWords>(c, c->lay.off_sync);
-  HIP_TRY(hipMemcpyAsync(c->pinned, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  // the pinned staging word, or (a context that allocates nothing) a host member
+  void* dst = c->pinned ? static_cast<void*>(c->pinned) : static_cast<void*>(&c->flags_host);
+  HIP_TRY(hipMemcpyAsync(dst, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  *flags = *reinterpret_cast<const uint32_t*>(c->pinned);
+  *flags = *static_cast<const uint32_t*>(dst);
   return SCO_OK;
 }
 
@@ -291,8 +294,11 @@ int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* byt
   return SCO_OK;
 }
 
-int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
-             size_t workspace_bytes, const int8_t* dev_init_spins, void* stream) {
+namespace {
+// noalloc: no pinned staging and no events (the context of sco_run_noalloc, which
+// allocates nothing); such a context serves launches, flags and observables only.
+int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
+              size_t workspace_bytes, const int8_t* dev_init_spins, void* stream, bool noalloc) {
   if (!out || !params || n_chains <= 0 || n_chains > SCO_MAXCHAINS || !dev_workspace) return SCO_EINVAL;
   *out = nullptr;
   if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) return SCO_EINVAL;
@@ -318,12 +324,15 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
     sco_destroy(c);
     return code;
   };
-  c->pinned_bytes = std::max<size_t>(4096, sizeof(ChainState) * n_chains + 64);
-  c->pinned_bytes = std::max(c->pinned_bytes, sizeof(unsigned long long) * 2 * n_chains + sizeof(double) * n_chains);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes, hipHostMallocDefault) != hipSuccess)
-    return fail(SCO_EHIP);
-  for (auto& e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) return fail(SCO_EHIP);
+  if (!noalloc) {
+    c->pinned_bytes = std::max<size_t>(4096, sizeof(ChainState) * n_chains + 64);
+    c->pinned_bytes =
+        std::max(c->pinned_bytes, sizeof(unsigned long long) * 2 * n_chains + sizeof(double) * n_chains);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(SCO_EHIP);
+    for (auto& e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(SCO_EHIP);
+  }
   if (hipMemsetAsync(at<char>(c, L.off_sync), 0, sizeof(SyncWords), c->stream) != hipSuccess) return fail(SCO_EHIP);
   if (hipMemsetAsync(at<char>(c, L.off_st), 0, sizeof(ChainState) * n_chains, c->stream) != hipSuccess)
     return fail(SCO_EHIP);
@@ -513,6 +522,12 @@ int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* 
   *out = c;
   return SCO_OK;
 }
+}  // namespace
+
+int sco_init(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
+             size_t workspace_bytes, const int8_t* dev_init_spins, void* stream) {
+  return init_impl(out, params, n_chains, dev_workspace, workspace_bytes, dev_init_spins, stream, false);
+}
 
 int sco_switch(sco_ctx* c, uint64_t step) {
   if (!c) return SCO_EINVAL;
@@ -558,6 +573,34 @@ int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
   }
   // a step that raised a flag ended at a barrier and every later launch did nothing
   return n_steps > 0 ? consume_flags(c) : SCO_OK;
+}
+
+int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* dev_spins_in,
+                    int8_t* dev_spins_out, uint64_t first_step, int n_steps, sco_obs* host_obs, void* stream) {
+  if (!params || n_chains <= 0 || n_chains > SCO_MAXCHAINS || !dev_spins_out || n_steps < 0) return SCO_EINVAL;
+  size_t need = 0;
+  int rc = sco_workspace_size(params, n_chains, &need);
+  if (rc) return rc;
+  if (need > static_cast<size_t>(SCO_NOALLOC_BYTES)) return SCO_ENOSPC;
+  void* scratch = nullptr;  // this GPU's copy of the library's static scratch array
+  if (sco_dev::noalloc_scratch(&scratch) != hipSuccess || !scratch) return SCO_EHIP;
+  sco_ctx* c = nullptr;
+  rc = init_impl(&c, params, n_chains, scratch, SCO_NOALLOC_BYTES, dev_spins_in, stream, true);
+  if (rc) return rc;
+  rc = sco_run(c, first_step, n_steps);
+  if (rc == SCO_OK && host_obs) rc = sco_observables(c, host_obs);
+  // the chains' spins, concatenated without padding
+  int64_t off = 0;
+  for (int ci = 0; ci < n_chains && rc == SCO_OK; ++ci) {
+    const ChainDesc& d = c->cd[ci];
+    if (hipMemcpyAsync(dev_spins_out + off, at<int8_t>(c, c->lay.off_spin) + d.vbase, d.N, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      rc = SCO_EHIP;
+    off += d.N;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && rc == SCO_OK) rc = SCO_EHIP;
+  sco_destroy(c);
+  return rc;
 }
 
 int sco_get_flags(sco_ctx* c, int64_t* last, int64_t* seen) {

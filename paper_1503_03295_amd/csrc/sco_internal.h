@@ -19,6 +19,7 @@
 #define SCO_SCAN_ITEMS 21       // values per thread of a degree-scan tile (21504-value tiles)
 #define SCO_GUIDE_BITS 14       // guide table of the cumulative couplings: 2^14 buckets
 #define SCO_BAR_GROUPS 32       // first-level arrival groups of the grid barrier
+#define SCO_NOALLOC_BYTES (64u << 20)  // static scratch of the entry point that allocates nothing
 
 enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4 };
 
@@ -117,4 +118,7 @@ hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_ch
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L,
                        int periodic, const int8_t* spin, int64_t vbase, uint32_t* bits,
                        double* prod, double* part, double* out);
+// Device address of the current GPU's copy of the static scratch array
+// (SCO_NOALLOC_BYTES, 256-byte aligned).
+hipError_t noalloc_scratch(void** ptr);
 }  // namespace sco_dev

@@ -21,6 +21,8 @@
 // the last bit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sco_internal.h"
 
 namespace {
@@ -2590,8 +2592,35 @@ extern "C" __global__ void k_obs_sum_final(const double* __restrict__ part, int 
   *out = s;
 }
 
+// =================================================================== static scratch
+// Device memory of the entry point that allocates nothing (sco_run_noalloc): the
+// workspace of its chains lives here.  Every GPU that loads the library holds one copy
+// until the process ends; calls on one GPU share it (and must not overlap).  In host
+// code `scratch` names only a host-side handle: kernels are given the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SCO_NOALLOC_BYTES];
+
 // =================================================================== host launchers
 namespace sco_dev {
+
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // with device `dev` current
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t table_j(hipStream_t s, const uint32_t* hd, int K, int L, int periodic, int n_images,
                    double D, double* J) {
