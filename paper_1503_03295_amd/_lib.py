@@ -15,7 +15,7 @@ EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
-    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags", "sco_counters", "sco_run_noalloc",
+    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags", "sco_counters", "sco_run_noalloc", "sco_run_graph",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
         "sco_sweep": ([P, u64, i32], i32),
         "sco_step": ([P, u64], i32),
         "sco_run": ([P, u64, i32], i32),
+        "sco_run_graph": ([P, u64, i32], i32),
         "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_counters": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_run_noalloc": ([ctypes.POINTER(ChainParamsC), i32, P, P, u64, i32, ctypes.POINTER(ObsC), P], i32),

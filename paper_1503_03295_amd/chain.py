@@ -118,6 +118,10 @@ class SCO:
     def run(self, first_step: int, n_steps: int) -> None:
         check(lib().sco_run(self._h, first_step, n_steps), "sco_run", self._h)
 
+    def run_graph(self, first_step: int, n_steps: int) -> None:
+        """The same steps as run(), replayed as one HIP graph of n_steps nodes."""
+        check(lib().sco_run_graph(self._h, first_step, n_steps), "sco_run_graph", self._h)
+
     # -- results
     def observables(self) -> list[dict]:
         out = (ObsC * self.n_chains)()

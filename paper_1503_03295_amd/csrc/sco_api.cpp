@@ -197,6 +197,13 @@ struct sco_ctx {
   int64_t flags_seen = 0;
   uint32_t last_flags = 0;  // flags of the last flagged launch consumed
   uint32_t flags_host = 0;  // read-back word when there is no pinned staging
+  // the step graph of sco_run_graph: n_steps cooperative k_step<7> nodes in a chain,
+  // built for one grid size; its nodes' arguments are rewritten for every replay
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<hipGraphNode_t> graph_nodes;
+  std::vector<StepArgs> graph_args;
+  int graph_blocks = 0;
 };
 
 namespace {
@@ -603,6 +610,86 @@ int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* 
   return rc;
 }
 
+namespace {
+void graph_release(sco_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_nodes.clear();
+  c->graph_args.clear();
+}
+
+// A graph of n full-step kernel nodes, each depending on the one before, every node
+// a cooperative launch of the schedule's grid.
+int graph_build(sco_ctx* c, int n) {
+  graph_release(c);
+  if (hipGraphCreate(&c->graph, 0) != hipSuccess) return SCO_EHIP;
+  c->graph_nodes.resize(n);
+  c->graph_args.assign(n, c->args);
+  for (int s = 0; s < n; ++s) {
+    void* kargs[] = {&c->graph_args[s]};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(sco_dev::step_kernel_full());
+    kp.gridDim = dim3(c->blocks);
+    kp.blockDim = dim3(SCO_CHUNK);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    const hipGraphNode_t* dep = s > 0 ? &c->graph_nodes[s - 1] : nullptr;
+    if (hipGraphAddKernelNode(&c->graph_nodes[s], c->graph, dep, s > 0 ? 1 : 0, &kp) != hipSuccess) {
+      graph_release(c);
+      return SCO_EHIP;
+    }
+    hipKernelNodeAttrValue v{};
+    v.cooperative = 1;
+    if (hipGraphKernelNodeSetAttribute(c->graph_nodes[s], hipKernelNodeAttributeCooperative, &v) != hipSuccess) {
+      graph_release(c);
+      return SCO_EHIP;
+    }
+  }
+  if (hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0) != hipSuccess) {
+    graph_release(c);
+    return SCO_EHIP;
+  }
+  c->graph_blocks = c->blocks;
+  return SCO_OK;
+}
+}  // namespace
+
+int sco_run_graph(sco_ctx* c, uint64_t first_step, int n_steps) {
+  if (!c || n_steps < 0) return SCO_EINVAL;
+  if (n_steps == 0) return SCO_OK;
+  if (first_step + static_cast<uint64_t>(n_steps) - 1 > 0xFFFFFFFFull) return SCO_EINVAL;
+  if (!c->graph_exec || static_cast<int>(c->graph_nodes.size()) != n_steps || c->graph_blocks != c->blocks) {
+    const int rc = graph_build(c, n_steps);
+    if (rc) return rc;
+  }
+  if (c->blocks != c->launched_blocks) {
+    HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, offsetof(SyncWords, flags), c->stream));
+    c->launched_blocks = c->blocks;
+  }
+  // this replay's step indices (and the current tile limit) into the nodes' arguments
+  for (int s = 0; s < n_steps; ++s) {
+    StepArgs& a = c->graph_args[s];
+    a = c->args;
+    a.trace = nullptr;
+    a.nsw_override = -1;
+    a.nsw_max = c->nsw_max;
+    a.step = static_cast<uint32_t>(first_step + static_cast<uint64_t>(s));
+    void* kargs[] = {&a};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(sco_dev::step_kernel_full());
+    kp.gridDim = dim3(c->blocks);
+    kp.blockDim = dim3(SCO_CHUNK);
+    kp.kernelParams = kargs;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(c->graph_exec, c->graph_nodes[s], &kp));
+  }
+  HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+  c->graph_state = 2;
+  return consume_flags(c);
+}
+
 int sco_get_flags(sco_ctx* c, int64_t* last, int64_t* seen) {
   if (!c) return SCO_EINVAL;
   if (last) *last = c->last_flags;
@@ -864,6 +951,7 @@ int sco_get_tables(sco_ctx* c, int chain, int32_t* K, int32_t* dx, int32_t* dy, 
 int sco_destroy(sco_ctx* c) {
   if (!c) return SCO_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  graph_release(c);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);

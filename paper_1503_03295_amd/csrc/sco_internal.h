@@ -112,6 +112,8 @@ hipError_t init_spins(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_c
                       const int64_t* src_base, const int8_t* src, int8_t* spin, int64_t G);
 int step_max_blocks();
 hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks);
+// The full step kernel (k_step<7>), for graph kernel nodes.
+const void* step_kernel_full();
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
                      const int8_t* spin, const uint16_t* color, unsigned long long* out,
                      unsigned* used, int64_t G);

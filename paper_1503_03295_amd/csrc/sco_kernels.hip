@@ -2664,6 +2664,8 @@ int step_max_blocks() {
   return best * cus;
 }
 
+const void* step_kernel_full() { return step_kernel_for(PH_SWITCH | PH_COLOR | PH_SWEEP); }
+
 hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks) {
   StepArgs copy = a;
   void* args[] = {&copy};

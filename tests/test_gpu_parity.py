@@ -94,6 +94,37 @@ def test_split_entry_points_equal_step():
     np.testing.assert_array_equal(a.spins(0), b.spins(0))
 
 
+def test_graph_replays_equal_plain_launches():
+    """sco_run_graph (a HIP graph of cooperative step nodes) gives the chains of
+    sco_run; the graph is replayed several times with eager work and
+    synchronisations between the replays, each replay checked."""
+    from paper_1503_03295_amd import SCO
+
+    params = [workloads.chain(128, True, 1.2, 2.0, chain_id=0, n_sw=2),
+              workloads.chain(40, False, 0.9, 1.0, chain_id=1)]
+    a = SCO([gpu_params(p) for p in params], device="cuda:0")
+    b = SCO([gpu_params(p) for p in params], device="cuda:0")
+    t = 0
+    for rep in range(4):
+        a.run(t, 3)
+        b.run_graph(t, 3)
+        t += 3
+        for c in range(len(params)):
+            np.testing.assert_array_equal(a.spins(c), b.spins(c), err_msg=f"replay {rep} chain {c}")
+            for x, y in zip(a.graph(c), b.graph(c)):
+                np.testing.assert_array_equal(x, y)
+        b.step(t)  # eager work between replays
+        a.step(t)
+        t += 1
+        assert [o["accepted"] for o in a.counters()] == [o["accepted"] for o in b.counters()]
+    # another length and another grid rebuild the graph
+    b.set_schedule(max(1, b.schedule()[0] // 2), 4096)
+    a.run(t, 2)
+    b.run_graph(t, 2)
+    for c in range(len(params)):
+        np.testing.assert_array_equal(a.spins(c), b.spins(c))
+
+
 def test_checkpoint_resume_exact():
     from paper_1503_03295_amd import SCO
 
