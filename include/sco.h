@@ -95,7 +95,22 @@ typedef struct {
                          other: switching targets within 1e-12 relative of C_top or of a
                          bracketing cumulative coupling, Metropolis draws |u - p| < 1e-12
                          (the only decisions a host evaluation may take differently) */
+  int32_t delta_sco;  /* maximum degree of the switched graph alone (Table 1's Delta) */
+  int32_t pad;
 } sco_obs;
+
+/* Statistics of one chain over one stage of an annealing schedule (sco_anneal). */
+typedef struct {
+  double T;                /* the stage's temperature */
+  double E;                /* full energy at the end of the stage */
+  int64_t M;               /* magnetisation at the end of the stage */
+  int64_t samples;         /* measured steps of the stage */
+  double abs_m, m2;        /* <|M|> / N and <M^2> / N^2 over the measured steps */
+  double k_mean;           /* <2 n_edges / N>: mean degree of the switched graph (Table 1's <k>) */
+  double delta_sco_mean;   /* mean of its maximum degree (Table 1's <Delta>) */
+  double delta_union_mean; /* mean maximum degree of the coloured union graph */
+  double acceptance;       /* accepted / attempted flips over the whole stage */
+} sco_stage;
 
 typedef struct sco_ctx sco_ctx;
 
@@ -157,6 +172,21 @@ int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* 
  * nodes' step indices and replay it.  The graph holds kernel nodes only.  Same results
  * as sco_run; synchronises and reports the steps' flags. */
 int sco_run_graph(sco_ctx* ctx, uint64_t first_step, int n_steps);
+
+/* Sets the temperature of one chain (chain = -1: every chain) for the steps that follow:
+ * beta, the bound rate (kappa + 1) beta J_m of the switching, the survival ratio and the
+ * pseudo-interactions of Eqs. (2)-(3) and the exchange-only acceptance are rebuilt
+ * (O(K) host work per chain).  Synchronises.  SCO_EINVAL for T <= 0 or not finite. */
+int sco_set_temperature(sco_ctx* ctx, int chain, double T);
+
+/* Annealing driver (the cooling protocol of Sec. 3.1): for each stage k = 0 .. n_stages-1,
+ * every chain c is set to temperature temps[k * n_chains + c], runs equil_steps SCO
+ * steps, then meas_steps steps whose magnetisation and graph statistics are summed
+ * exactly on the device; out[k * n_chains + c] receives the stage's statistics.  Stage k
+ * uses the step indices first_step + k (equil_steps + meas_steps) onwards, so the run
+ * equals sco_set_temperature + sco_run stage by stage.  Synchronises after each stage. */
+int sco_anneal(sco_ctx* ctx, const double* temps, int n_stages, int equil_steps, int meas_steps,
+               uint64_t first_step, sco_stage* out);
 
 /* Device flags (SCO_FLAG bits as in sco_obs.flags) of the last flagged launch that a
  * synchronising call consumed, and all flags seen since the last counter reset. */

@@ -52,7 +52,7 @@ class Obs(ctypes.Structure):
         ("delta_union", ctypes.c_int32), ("q", ctypes.c_int32), ("colors_used", ctypes.c_int32),
         ("kw_levels", ctypes.c_int32),
         ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
-        ("near_ties", ctypes.c_int64),
+        ("near_ties", ctypes.c_int64), ("delta_sco", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -99,6 +99,7 @@ def lib():
         L.orc_get_kw_rounds.argtypes = [P, P]; L.orc_get_kw_rounds.restype = None
         L.orc_partner.argtypes = [P, ctypes.c_int, ctypes.c_int]; L.orc_partner.restype = ctypes.c_int
         L.orc_reset_counters.argtypes = [P]; L.orc_reset_counters.restype = None
+        L.orc_set_temperature.argtypes = [P, ctypes.c_double]; L.orc_set_temperature.restype = ctypes.c_int
         L.orc_survival_counts.argtypes = [P, ctypes.c_uint64, ctypes.c_int, P]
         L.orc_survival_counts.restype = None
         L.orc_run_record.argtypes = [P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, P, P]
@@ -229,6 +230,13 @@ class OracleChain:
     def reset_counters(self) -> None:
         lib().orc_reset_counters(self._h)
 
+    def set_temperature(self, T: float) -> None:
+        if lib().orc_set_temperature(self._h, float(T)) != 0:
+            raise ValueError(f"invalid temperature {T}")
+        self.params.T = float(T)
+        self._p.T = float(T)
+
+
     def observables(self, dipolar: str = "auto") -> dict:
         """dipolar: 'direct' (pair sum in C), 'fft' (periodic only), 'none' or 'auto'."""
         if dipolar == "auto":
@@ -281,3 +289,43 @@ def dipolar_energy_fft(spins: np.ndarray, L: int, tables: dict) -> float:
     for j, c in zip(J.tolist(), cm.tolist()):  # sequential, table order
         acc += j * float(c)
     return acc
+
+
+def anneal(chain: OracleChain, temps, equil_steps: int, meas_steps: int, first_step: int = 0) -> list[dict]:
+    """The cooling protocol of Sec. 3.1 run by the oracle: per temperature, equil_steps
+    SCO steps, then meas_steps steps whose |M|, M^2, bond count and maximum degrees are
+    summed as exact integers; returns the per-stage means (divided in the order
+    sum / samples / N) and the state at the end of each stage."""
+    out = []
+    t = first_step
+    N = float(chain.N)
+    for T in temps:
+        chain.set_temperature(T)
+        acc0 = chain.observables(dipolar="none")
+        for _ in range(equil_steps):
+            chain.step(t)
+            t += 1
+        s_abs = s_m2 = s_b = s_ds = s_du = 0
+        for _ in range(meas_steps):
+            chain.step(t)
+            t += 1
+            o = chain.observables(dipolar="none")
+            m = abs(int(o["M"]))
+            s_abs += m
+            s_m2 += m * m
+            s_b += 2 * int(o["n_edges"])
+            s_ds += int(o["delta_sco"])
+            s_du += int(o["delta_union"])
+        o = chain.observables()
+        ns = float(meas_steps)
+        att = o["attempts"] - acc0["attempts"]
+        out.append(dict(
+            T=float(T), E=o["E"], M=int(o["M"]), samples=meas_steps,
+            abs_m=(float(s_abs) / ns / N) if meas_steps else 0.0,
+            m2=(float(s_m2) / ns / (N * N)) if meas_steps else 0.0,
+            k_mean=(float(s_b) / ns / N) if meas_steps else 0.0,
+            delta_sco_mean=(float(s_ds) / ns) if meas_steps else 0.0,
+            delta_union_mean=(float(s_du) / ns) if meas_steps else 0.0,
+            acceptance=(float(o["accepted"] - acc0["accepted"]) / att) if att else 0.0,
+            spins=chain.spins))
+    return out

@@ -51,6 +51,7 @@ typedef struct {
   int64_t M, n_edges;
   int32_t delta_union, q, colors_used, kw_levels;
   int64_t kw_rounds, accepted, attempts, near_ties;
+  int32_t delta_sco, pad; /* maximum degree of the switched graph alone */
 } orc_obs;
 
 enum { TAG_INIT = 1, TAG_SW = 2, TAG_TH = 3, TAG_MC = 4 };
@@ -175,6 +176,34 @@ static int neighbours(const orc_chain* c, int v, int nb[4]) {
   return n;
 }
 
+/* The temperature-dependent columns of the table at beta = 1/T. */
+static void temperature_columns(orc_chain* c) {
+  const orc_params* p = &c->p;
+  for (int m = 0; m < c->K; ++m) {
+    double Jd = c->Jm[m];
+    /* Eq. (2) with V = J s_i s_j and V^max = kappa J:
+     *   P(parallel) = exp(-beta (kappa-1) J), P(antiparallel) = exp(-beta (kappa+1) J).
+     * A candidate (probability 1-P(antiparallel)) survives with probability
+     * (1-P)/(1-P(antiparallel)): 1 for antiparallel, theta for parallel. */
+    double em = expm1(-c->beta * (p->kappa + 1.0) * Jd);
+    double ep = expm1(-c->beta * (p->kappa - 1.0) * Jd);
+    c->theta[m] = c->hard ? 0.0 : ep / em;
+    /* Eq. (3): Vbar(s) = J s - T log(1 - P(s)); delta = Vbar(+1) - Vbar(-1). */
+    c->delta[m] = c->hard ? INFINITY : 2.0 * Jd + p->T * log(em / ep);
+  }
+}
+
+/* A new temperature for the steps that follow (the cooling protocol of Sec. 3.1):
+ * beta, the bound rate and the columns of Eqs. (2)-(3).  Returns -1 for T <= 0. */
+int orc_set_temperature(orc_chain* c, double T) {
+  if (!(T > 0.0)) return -1;
+  c->p.T = T;
+  c->beta = 1.0 / T;
+  c->inv_rate = T / (c->p.kappa + 1.0);
+  temperature_columns(c);
+  return 0;
+}
+
 void orc_destroy(orc_chain* c) {
   if (!c) return;
   free(c->hdx); free(c->hdy); free(c->Jm); free(c->Cm); free(c->theta); free(c->delta);
@@ -234,17 +263,9 @@ orc_chain* orc_create(const orc_params* p, const int8_t* init_spins) {
     c->Jm[m] = Jd;
     acc += Jd;
     c->Cm[m] = acc;
-    /* Eq. (2) with V = J s_i s_j and V^max = kappa J:
-     *   P(parallel) = exp(-beta (kappa-1) J), P(antiparallel) = exp(-beta (kappa+1) J).
-     * A candidate (probability 1-P(antiparallel)) survives with probability
-     * (1-P)/(1-P(antiparallel)): 1 for antiparallel, theta for parallel. */
-    double em = expm1(-c->beta * (p->kappa + 1.0) * Jd);
-    double ep = expm1(-c->beta * (p->kappa - 1.0) * Jd);
-    c->theta[m] = c->hard ? 0.0 : ep / em;
-    /* Eq. (3): Vbar(s) = J s - T log(1 - P(s)); delta = Vbar(+1) - Vbar(-1). */
-    c->delta[m] = c->hard ? INFINITY : 2.0 * Jd + p->T * log(em / ep);
   }
   free(d);
+  temperature_columns(c);
 
   c->s = (int8_t*)malloc((size_t)N);
   for (int v = 0; v < N; ++v) {
@@ -547,6 +568,11 @@ void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
   o->accepted = c->accepted;
   o->attempts = c->attempts;
   o->near_ties = c->near_ties;
+  int dmax = 0;
+  for (int v = 0; v < N; ++v)
+    if (c->row_ptr[v + 1] - c->row_ptr[v] > dmax) dmax = c->row_ptr[v + 1] - c->row_ptr[v];
+  o->delta_sco = dmax;
+  o->pad = 0;
 }
 
 /* ----------------------------------------------------------- accessors */

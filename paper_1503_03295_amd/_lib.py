@@ -16,6 +16,7 @@ EXPORTS = [
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
     "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags", "sco_counters", "sco_run_noalloc", "sco_run_graph",
+    "sco_set_temperature", "sco_anneal",
 ]
 
 
@@ -38,6 +39,7 @@ class ObsC(ctypes.Structure):
         ("kw_levels", ctypes.c_int32),
         ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
         ("rechecks", ctypes.c_int64), ("flags", ctypes.c_int64), ("near_ties", ctypes.c_int64),
+        ("delta_sco", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -46,6 +48,18 @@ class ObsC(ctypes.Structure):
 
 def flag_names(flags: int) -> str:
     return ", ".join(n for b, n in FLAG_NAMES.items() if flags & b) or "none"
+
+
+class StageC(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_double), ("E", ctypes.c_double), ("M", ctypes.c_int64), ("samples", ctypes.c_int64),
+        ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("k_mean", ctypes.c_double),
+        ("delta_sco_mean", ctypes.c_double), ("delta_union_mean", ctypes.c_double),
+        ("acceptance", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ScoError(RuntimeError):
@@ -79,6 +93,8 @@ def lib():
         "sco_step": ([P, u64], i32),
         "sco_run": ([P, u64, i32], i32),
         "sco_run_graph": ([P, u64, i32], i32),
+        "sco_set_temperature": ([P, i32, ctypes.c_double], i32),
+        "sco_anneal": ([P, ctypes.POINTER(ctypes.c_double), i32, i32, i32, u64, ctypes.POINTER(StageC)], i32),
         "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_counters": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_run_noalloc": ([ctypes.POINTER(ChainParamsC), i32, P, P, u64, i32, ctypes.POINTER(ObsC), P], i32),

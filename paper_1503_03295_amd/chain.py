@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ChainParamsC, ObsC, check, lib
+from ._lib import ChainParamsC, ObsC, StageC, check, lib
 
 
 @dataclass
@@ -121,6 +121,27 @@ class SCO:
     def run_graph(self, first_step: int, n_steps: int) -> None:
         """The same steps as run(), replayed as one HIP graph of n_steps nodes."""
         check(lib().sco_run_graph(self._h, first_step, n_steps), "sco_run_graph", self._h)
+
+    # -- temperature schedule
+    def set_temperature(self, T: float, chain: int = -1) -> None:
+        check(lib().sco_set_temperature(self._h, chain, float(T)), "sco_set_temperature", self._h)
+        for c in (range(self.n_chains) if chain < 0 else [chain]):
+            self.params[c].T = float(T)
+
+    def anneal(self, temps, equil_steps: int, meas_steps: int, first_step: int = 0) -> list[list[dict]]:
+        """temps: n_stages x n_chains temperatures (or a 1-D schedule shared by all
+        chains); returns per stage the statistics of every chain."""
+        t = np.asarray(temps, dtype=np.float64)
+        if t.ndim == 1:
+            t = np.repeat(t[:, None], self.n_chains, axis=1)
+        t = np.ascontiguousarray(t)
+        ns = t.shape[0]
+        out = (StageC * (ns * self.n_chains))()
+        check(lib().sco_anneal(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ns, int(equil_steps),
+                               int(meas_steps), int(first_step), out), "sco_anneal", self._h)
+        for c in range(self.n_chains):
+            self.params[c].T = float(t[-1, c]) if ns else self.params[c].T
+        return [[out[k * self.n_chains + c].as_dict() for c in range(self.n_chains)] for k in range(ns)]
 
     # -- results
     def observables(self) -> list[dict]:

@@ -54,6 +54,7 @@ struct Layout {
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
+  size_t off_acc = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -138,6 +139,7 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_prod = take(sizeof(double) * lay.maxK);
   lay.off_dpart = take(sizeof(double) * (lay.maxK / 4096 + 2));
   lay.off_dres = take(sizeof(double) * n);
+  lay.off_acc = take(sizeof(AnnealAcc) * n);
   lay.bytes = off;
   return SCO_OK;
 }
@@ -302,6 +304,67 @@ int sco_workspace_size(const sco_chain_params* params, int n_chains, size_t* byt
 }
 
 namespace {
+// The temperature-dependent part of a chain (Eqs. 2-3 at beta = 1/T): the descriptor's
+// beta, rate and exchange-only acceptance, and for kappa > 1 the survival ratio theta
+// and the pseudo-interaction difference delta of every displacement, uploaded to the
+// workspace (synchronous; the descriptor itself is uploaded by the caller).
+int temperature_tables(sco_ctx* c, int ci, double T) {
+  const Layout& L = c->lay;
+  sco_chain_params& p = c->params[ci];
+  p.T = T;
+  ChainDesc& d = c->cd[ci];
+  const double beta = 1.0 / T;
+  d.beta = beta;
+  d.neg_beta = -beta;
+  d.inv_rate = T / (p.kappa + 1.0);
+  d.inv_rate32 = static_cast<float>(d.inv_rate);
+  d.neg_beta32 = static_cast<float>(-beta);
+  // an FP32 gap decision is at least inv_rate 2^-20 from the compared table value;
+  // it may stand only where no near tie (1e-12 relative) of the FP64 gap can hide
+  d.fp32_gap = d.inv_rate * 0x1p-20 > 2e-12 * d.C_top ? 1 : 0;
+  for (int k = -4; k <= 4; ++k) {
+    const double dE = (2.0 * p.J) * static_cast<double>(k);
+    d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
+  }
+  if (d.hard) return SCO_OK;
+  const int t = L.chain_table[ci];
+  const int64_t K = L.table_K[t];
+  std::vector<double>& th = c->theta[ci];
+  std::vector<double>& de = c->delta[ci];
+  std::vector<float> de32(K);
+  th.resize(K);
+  de.resize(K);
+  const std::vector<double>& Jt = c->J[t];
+  for (int64_t m = 0; m < K; ++m) {
+    const double em = std::expm1(-beta * (p.kappa + 1.0) * Jt[m]);
+    const double ep = std::expm1(-beta * (p.kappa - 1.0) * Jt[m]);
+    th[m] = ep / em;
+    de[m] = 2.0 * Jt[m] + T * std::log(em / ep);
+    de32[m] = static_cast<float>(de[m]);
+  }
+  HIP_TRY(hipMemcpyAsync(const_cast<double*>(d.theta), th.data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(const_cast<double*>(d.delta), de.data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(const_cast<float*>(d.delta32), de32.data(), sizeof(float) * K, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+// st[c].mag of every chain from its spins (after the spins were set from outside)
+int refresh_mag(sco_ctx* c) {
+  const Layout& L = c->lay;
+  unsigned long long* d_obs = at<unsigned long long>(c, L.off_obs);
+  HIP_TRY(hipMemsetAsync(d_obs, 0, sizeof(unsigned long long) * 2 * c->n, c->stream));
+  HIP_TRY(hipMemsetAsync(at<uint32_t>(c, L.off_used), 0, sizeof(uint32_t) * SCO_QWORDS * c->n, c->stream));
+  HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
+                             at<int8_t>(c, L.off_spin), at<uint16_t>(c, L.off_color), d_obs,
+                             at<uint32_t>(c, L.off_used), L.G));
+  HIP_TRY(sco_dev::set_mag(c->stream, at<ChainState>(c, L.off_st), d_obs, c->n));
+  return SCO_OK;
+}
+
 // noalloc: no pinned staging and no events (the context of sco_run_noalloc, which
 // allocates nothing); such a context serves launches, flags and observables only.
 int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void* dev_workspace,
@@ -400,7 +463,6 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
     const sco_chain_params& p = params[ci];
     const int t = L.chain_table[ci];
     const int64_t K = L.table_K[t];
-    const double beta = 1.0 / p.T;
     const bool hard = p.kappa == 1.0;
     ChainDesc d{};
     d.L = p.L;
@@ -416,53 +478,22 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
     d.guide_inv = static_cast<double>(kNB) / d.C_top;
     d.nguide = kNB;
     d.twoJ = 2.0 * p.J;
-    d.beta = beta;
-    d.neg_beta = -beta;
     d.inv_L = 1.0 / p.L;
-    d.inv_rate = p.T / (p.kappa + 1.0);
-    d.inv_rate32 = static_cast<float>(d.inv_rate);
-    d.neg_beta32 = static_cast<float>(-beta);
     d.twoJ32 = static_cast<float>(d.twoJ);
     d.twoJ32_exact = static_cast<double>(d.twoJ32) == d.twoJ ? 1 : 0;
-    // an FP32 gap decision is at least inv_rate 2^-20 from the compared table value;
-    // it may stand only where no near tie (1e-12 relative) of the FP64 gap can hide
-    d.fp32_gap = d.inv_rate * 0x1p-20 > 2e-12 * d.C_top ? 1 : 0;
-    for (int k = -4; k <= 4; ++k) {
-      const double dE = (2.0 * p.J) * static_cast<double>(k);
-      d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
-    }
     d.seed = p.seed;
     d.chain_id = p.chain_id;
     d.hard = hard ? 1 : 0;
     d.precision = p.precision;
     d.n_sw = p.n_sw;
     if (!hard) {
-      std::vector<double>& th = c->theta[ci];
-      std::vector<double>& de = c->delta[ci];
-      std::vector<float> de32(K);
-      th.resize(K);
-      de.resize(K);
-      const std::vector<double>& Jt = c->J[t];
-      for (int64_t m = 0; m < K; ++m) {
-        const double em = std::expm1(-beta * (p.kappa + 1.0) * Jt[m]);
-        const double ep = std::expm1(-beta * (p.kappa - 1.0) * Jt[m]);
-        th[m] = ep / em;
-        de[m] = 2.0 * Jt[m] + p.T * std::log(em / ep);
-        de32[m] = static_cast<float>(de[m]);
-      }
       d.theta = at<double>(c, L.off_theta[ci]);
       d.delta = at<double>(c, L.off_delta[ci]);
       d.delta32 = at<float>(c, L.off_delta32[ci]);
-      if (hipMemcpyAsync(const_cast<double*>(d.theta), th.data(), sizeof(double) * K, hipMemcpyHostToDevice,
-                         c->stream) != hipSuccess ||
-          hipMemcpyAsync(const_cast<double*>(d.delta), de.data(), sizeof(double) * K, hipMemcpyHostToDevice,
-                         c->stream) != hipSuccess ||
-          hipMemcpyAsync(const_cast<float*>(d.delta32), de32.data(), sizeof(float) * K, hipMemcpyHostToDevice,
-                         c->stream) != hipSuccess)
-        return fail(SCO_EHIP);
-      if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
     }
     c->cd[ci] = d;
+    const int tr = temperature_tables(c, ci, p.T);
+    if (tr) return fail(tr);
     const int64_t ch0 = L.vbase[ci] / SCO_CHUNK, chn = (static_cast<int64_t>(d.N) + SCO_CHUNK - 1) / SCO_CHUNK;
     for (int64_t ch = ch0; ch < ch0 + chn; ++ch) chunk_chain[ch] = ci;
     src_base[ci] = sb;
@@ -525,6 +556,12 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   // rewritten by the tile levels of every colouring before any level reads them)
   if (hipMemsetAsync(at<uint32_t>(c, L.off_word), 0xFF, sizeof(uint32_t) * L.G, c->stream) != hipSuccess)
     return fail(SCO_EHIP);
+  if (hipMemsetAsync(at<uint16_t>(c, L.off_color), 0, sizeof(uint16_t) * L.G, c->stream) != hipSuccess)
+    return fail(SCO_EHIP);
+  {
+    const int mr = refresh_mag(c);
+    if (mr) return fail(mr);
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SCO_EHIP);
   *out = c;
   return SCO_OK;
@@ -690,6 +727,78 @@ int sco_run_graph(sco_ctx* c, uint64_t first_step, int n_steps) {
   return consume_flags(c);
 }
 
+int sco_set_temperature(sco_ctx* c, int chain, double T) {
+  if (!c || chain < -1 || chain >= c->n || !(T > 0.0) || !std::isfinite(T)) return SCO_EINVAL;
+  const int c0 = chain < 0 ? 0 : chain, c1 = chain < 0 ? c->n : chain + 1;
+  for (int ci = c0; ci < c1; ++ci) {
+    const int rc = temperature_tables(c, ci, T);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(at<ChainDesc>(c, c->lay.off_cd) + c0, c->cd.data() + c0, sizeof(ChainDesc) * (c1 - c0),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+int sco_anneal(sco_ctx* c, const double* temps, int n_stages, int equil_steps, int meas_steps,
+               uint64_t first_step, sco_stage* out) {
+  if (!c || !temps || !out || n_stages < 0 || equil_steps < 0 || meas_steps < 0) return SCO_EINVAL;
+  for (int64_t i = 0; i < static_cast<int64_t>(n_stages) * c->n; ++i)
+    if (!(temps[i] > 0.0) || !std::isfinite(temps[i])) return SCO_EINVAL;
+  const Layout& L = c->lay;
+  AnnealAcc* acc = at<AnnealAcc>(c, L.off_acc);
+  std::vector<AnnealAcc> h(c->n);
+  std::vector<ChainState> st0(c->n), st1(c->n);
+  uint64_t step = first_step;
+  for (int k = 0; k < n_stages; ++k) {
+    for (int ci = 0; ci < c->n; ++ci) {
+      const int rc = temperature_tables(c, ci, temps[static_cast<int64_t>(k) * c->n + ci]);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(at<ChainDesc>(c, L.off_cd), c->cd.data(), sizeof(ChainDesc) * c->n,
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(st0.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int rc = sco_run(c, step, equil_steps);
+    if (rc) return rc;
+    step += static_cast<uint64_t>(equil_steps);
+    HIP_TRY(hipMemsetAsync(acc, 0, sizeof(AnnealAcc) * c->n, c->stream));
+    for (int s = 0; s < meas_steps; ++s, ++step) {
+      rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, step, -1);
+      if (rc) return rc;
+      HIP_TRY(sco_dev::anneal_acc(c->stream, at<ChainState>(c, L.off_st), acc, c->n));
+    }
+    c->graph_state = 2;
+    rc = consume_flags(c);  // synchronises
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(h.data(), acc, sizeof(AnnealAcc) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(st1.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<sco_obs> obs(c->n);
+    rc = sco_observables(c, obs.data());
+    if (rc) return rc;
+    for (int ci = 0; ci < c->n; ++ci) {
+      sco_stage& o = out[static_cast<int64_t>(k) * c->n + ci];
+      const double N = static_cast<double>(c->cd[ci].N);
+      const double ns = static_cast<double>(h[ci].samples);
+      o.T = c->params[ci].T;
+      o.E = obs[ci].E;
+      o.M = obs[ci].M;
+      o.samples = static_cast<int64_t>(h[ci].samples);
+      o.abs_m = ns > 0 ? static_cast<double>(h[ci].abs_m) / ns / N : 0.0;
+      o.m2 = ns > 0 ? static_cast<double>(h[ci].m2) / ns / (N * N) : 0.0;
+      o.k_mean = ns > 0 ? static_cast<double>(h[ci].bonds) / ns / N : 0.0;
+      o.delta_sco_mean = ns > 0 ? static_cast<double>(h[ci].delta_sco) / ns : 0.0;
+      o.delta_union_mean = ns > 0 ? static_cast<double>(h[ci].delta_union) / ns : 0.0;
+      const double att = static_cast<double>(st1[ci].attempts - st0[ci].attempts);
+      o.acceptance = att > 0 ? static_cast<double>(st1[ci].accepted - st0[ci].accepted) / att : 0.0;
+    }
+  }
+  return SCO_OK;
+}
+
 int sco_get_flags(sco_ctx* c, int64_t* last, int64_t* seen) {
   if (!c) return SCO_EINVAL;
   if (last) *last = c->last_flags;
@@ -847,10 +956,13 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   else
     std::fill(edip.begin(), edip.end(), std::nan(""));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  int bad_mag = 0;
   for (int ci = 0; ci < c->n; ++ci) {
     sco_obs& o = out[ci];
     const ChainState& s = st[ci];
     o.M = static_cast<long long>(sums[2 * ci]);
+    // the magnetisation the sweeps keep must equal the sum of the spins
+    if (s.mag != o.M) bad_mag = 1;
     o.E_exchange = -c->params[ci].J * static_cast<double>(static_cast<long long>(sums[2 * ci + 1]));
     o.E_dipolar = edip[ci];
     o.E = o.E_exchange + o.E_dipolar;
@@ -869,7 +981,9 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
     o.rechecks = static_cast<int64_t>(s.rechecks);
     o.flags = c->flags_seen;
     o.near_ties = static_cast<int64_t>(s.near_ties);
+    o.delta_sco = s.delta_sco;
   }
+  if (fr == SCO_OK && bad_mag) return SCO_EINTERNAL;
   return fr;
 }
 }  // namespace
@@ -892,6 +1006,8 @@ int sco_set_spins(sco_ctx* c, int chain, const int8_t* host_in) {
   std::vector<int8_t> s(d.N);
   for (int v = 0; v < d.N; ++v) s[v] = host_in[v] > 0 ? 1 : -1;
   HIP_TRY(hipMemcpyAsync(at<int8_t>(c, c->lay.off_spin) + d.vbase, s.data(), d.N, hipMemcpyHostToDevice, c->stream));
+  const int mr = refresh_mag(c);
+  if (mr) return mr;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return SCO_OK;
 }

@@ -50,9 +50,15 @@ struct ChainDesc {
 struct ChainState {
   int32_t delta_union, q, M, P;  // palette, KW levels, levels run inside one LDS tile
   uint32_t n_edges;              // directed surviving bonds of the last switching
-  int32_t colors_used;
+  int32_t delta_sco;             // maximum degree of the switched (bond) graph alone
   unsigned long long accepted, attempts, rechecks, near_ties;
+  long long mag;                 // sum of the spins, kept current by the sweeps' flips
   int32_t kw_rounds[SCO_MAXLEVEL];
+};
+
+// Per-chain sums over the measured steps of an annealing stage (exact integers).
+struct AnnealAcc {
+  unsigned long long samples, abs_m, m2, bonds, delta_sco, delta_union;
 };
 
 // Device-wide synchronisation words (each counter on its own 128-byte line).
@@ -117,6 +123,10 @@ const void* step_kernel_full();
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
                      const int8_t* spin, const uint16_t* color, unsigned long long* out,
                      unsigned* used, int64_t G);
+// st[c].mag = out[2 c] (the spin sums of obs_basic) for every chain
+hipError_t set_mag(hipStream_t s, ChainState* st, const unsigned long long* out, int n);
+// acc[c] += this step's |M|, M^2, directed bonds and maximum degrees
+hipError_t anneal_acc(hipStream_t s, const ChainState* st, AnnealAcc* acc, int n);
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L,
                        int periodic, const int8_t* spin, int64_t vbase, uint32_t* bits,
                        double* prod, double* part, double* out);

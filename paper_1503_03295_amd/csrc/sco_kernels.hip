@@ -1001,12 +1001,13 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
 // per block.
 constexpr int kScanRow = 8;
 __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q, int q_cap) {
-  __shared__ int32_t rmax[SCO_MAXCHAINS];
-  __shared__ int32_t rsum[SCO_MAXCHAINS];
+  __shared__ int32_t rmax[SCO_MAXCHAINS];  // union degree
+  __shared__ int32_t rsum[SCO_MAXCHAINS];  // bonds
+  __shared__ int32_t rbmx[SCO_MAXCHAINS];  // bond degree
   __shared__ int32_t s_nq;
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
-  for (int c = threadIdx.x; c < a.n_chains; c += kBlock) rmax[c] = rsum[c] = 0;
+  for (int c = threadIdx.x; c < a.n_chains; c += kBlock) rmax[c] = rsum[c] = rbmx[c] = 0;
   if (threadIdx.x == 0) s_nq = 0;
   __syncthreads();
   // the full path for up to kScan sites per thread (g < 0: none): row read in one
@@ -1109,6 +1110,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
       }
       const int c = ok[r] ? cs[r] : -1;
       wave_max_to(rmax, c, udeg);
+      wave_max_to(rbmx, c, rowlen);
       wave_sum_to(rsum, c, rowlen);
     }
   };
@@ -1185,6 +1187,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
   __syncthreads();
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
     if (rmax[c] > 0) atomicMax(&a.st[c].delta_union, rmax[c]);
+    if (rbmx[c] > 0) atomicMax(&a.st[c].delta_sco, rbmx[c]);
     if (rsum[c] > 0) atomicAdd(&a.st[c].n_edges, static_cast<uint32_t>(rsum[c]));
   }
 }
@@ -1960,7 +1963,9 @@ constexpr int kLocalChains = 4;  // chain descriptors of a block's range held in
 __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
   __shared__ int32_t bfill[SCO_MAXQ];
-  __shared__ unsigned long long bacc[SCO_MAXCHAINS];  // accepted flips of the block per chain
+  // accepted flips of the block per chain: up -> down in the low 32 bits, down -> up in
+  // the high 32 bits (the magnetisation moves by 2 (high - low))
+  __shared__ unsigned long long bacc[SCO_MAXCHAINS];
   __shared__ ChainDesc lcd[kLocalChains];
   const int qmax = static_cast<int>(a.sync->qmax);
   const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
@@ -1973,6 +1978,21 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
   const bool local_cd = c_hi - c_lo < kLocalChains;
   Tally tally(c_lo);
+  // the block's flip counts into the chain states (accepted flips, magnetisation)
+  auto flush_flips = [&]() {
+    __syncthreads();
+    for (int c = tid; c < a.n_chains; c += kBlock) {
+      const unsigned long long f = bacc[c];
+      if (f) {
+        const unsigned long long lo = f & 0xFFFFFFFFull, hi = f >> 32;
+        atomicAdd(&a.st[c].accepted, lo + hi);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.st[c].mag), 2ull * (hi - lo));  // two's complement
+        bacc[c] = 0;
+      }
+    }
+    __syncthreads();
+  };
+  const bool flush_each_sweep = static_cast<int64_t>(a.nsw_max) * (r1 - r0) >= (1ll << 31);
   if (local_cd)
     for (int i = tid; i <= c_hi - c_lo; i += kBlock) lcd[i] = a.cd[c_lo + i];
   for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
@@ -2278,10 +2298,12 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
             const int c = live[r] ? cs[r] : -1;
             const int c0 = __shfl(c, 0);
             if (__ballot(c != c0 && c >= 0) == 0) {
-              const uint64_t mk = __ballot(acc[r]);
-              if (lane_id() == 0 && mk && c0 >= 0) atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(mk)));
+              const uint64_t md = __ballot(acc[r] && sv[r] > 0), mu = __ballot(acc[r] && sv[r] < 0);
+              if (lane_id() == 0 && (md | mu) && c0 >= 0)
+                atomicAdd(&bacc[c0], static_cast<unsigned long long>(__popcll(md)) |
+                                         (static_cast<unsigned long long>(__popcll(mu)) << 32));
             } else if (acc[r]) {
-              atomicAdd(&bacc[c], 1ull);
+              atomicAdd(&bacc[c], sv[r] > 0 ? 1ull : 1ull << 32);
             }
           }
         }
@@ -2291,6 +2313,9 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
         if (!(last ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
         mark(a.trace, 1000 + cc);
       }
+      // each half of a block's count stays below 2^32 (flushed every sweep when the
+      // whole phase could reach it)
+      if (flush_each_sweep && s + 1 < a.nsw_max) flush_flips();
     }
     return true;
   };
@@ -2310,8 +2335,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   else ok = body(lst_mem, [&](int c) -> const ChainDesc& { return a.cd[c]; }, Flag<false>{});
   if (!ok) return false;
   tally.flush(a);
-  for (int c = tid; c < a.n_chains; c += kBlock)
-    if (bacc[c]) atomicAdd(&a.st[c].accepted, bacc[c]);
+  flush_flips();
   if (blockIdx.x == 0)
     for (int c = tid; c < a.n_chains; c += kBlock) {
       const int nsw = a.nsw_override >= 0 ? a.nsw_override : a.cd[c].n_sw;
@@ -2349,6 +2373,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     }
     for (int c = gtid(); c < a.n_chains; c += stride) {
       a.st[c].delta_union = 0;
+      a.st[c].delta_sco = 0;
       a.st[c].n_edges = 0;
       for (int p = 0; p < SCO_MAXLEVEL; ++p) a.st[c].kw_rounds[p] = 0;
     }
@@ -2461,6 +2486,29 @@ extern "C" __global__ void __launch_bounds__(kBlock)
   }
   if (threadIdx.x < SCO_QWORDS && s_used[threadIdx.x])
     atomicOr(&used[c * SCO_QWORDS + threadIdx.x], s_used[threadIdx.x]);
+}
+
+// st[c].mag from the spin sums of k_obs_basic (after the spins were set from outside).
+extern "C" __global__ void k_set_mag(ChainState* __restrict__ st, const unsigned long long* __restrict__ out,
+                                     int n) {
+  const int c = static_cast<int>(gtid());
+  if (c < n) st[c].mag = static_cast<long long>(out[2 * c]);
+}
+
+// One measured step of an annealing stage: per chain |M|, M^2, the directed bonds and
+// the two maximum degrees of the step's graph, summed exactly.
+extern "C" __global__ void k_anneal_acc(const ChainState* __restrict__ st, AnnealAcc* __restrict__ acc, int n) {
+  const int c = static_cast<int>(gtid());
+  if (c >= n) return;
+  const long long m = st[c].mag;
+  const unsigned long long am = static_cast<unsigned long long>(m < 0 ? -m : m);
+  AnnealAcc& x = acc[c];
+  x.samples += 1ull;
+  x.abs_m += am;
+  x.m2 += am * am;
+  x.bonds += st[c].n_edges;
+  x.delta_sco += static_cast<unsigned long long>(st[c].delta_sco);
+  x.delta_union += static_cast<unsigned long long>(st[c].delta_union);
 }
 
 // Spins of one chain as bit rows: bit x of row y set when s(x, y) = -1; W words a row.
@@ -2676,6 +2724,16 @@ hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_ch
                      const uint16_t* color, unsigned long long* out, unsigned* used, int64_t G) {
   hipLaunchKernelGGL(k_obs_basic, dim3(static_cast<uint32_t>(G / kBlock)), dim3(kBlock), 0, s, cd,
                      chunk_chain, spin, color, out, used, G);
+  return hipGetLastError();
+}
+
+hipError_t set_mag(hipStream_t s, ChainState* st, const unsigned long long* out, int n) {
+  hipLaunchKernelGGL(k_set_mag, dim3((n + 255) / 256), dim3(256), 0, s, st, out, n);
+  return hipGetLastError();
+}
+
+hipError_t anneal_acc(hipStream_t s, const ChainState* st, AnnealAcc* acc, int n) {
+  hipLaunchKernelGGL(k_anneal_acc, dim3((n + 255) / 256), dim3(256), 0, s, st, acc, n);
   return hipGetLastError();
 }
 

@@ -143,3 +143,25 @@ def test_switching_and_pseudo_columns(kappa):
         vbar_m = -Jm - mp.mpf(T) * mp.log(1 - Panti)
         assert t["theta"][m] == pytest.approx(float(theta), rel=1e-14)
         assert t["delta"][m] == pytest.approx(float(vbar_p - vbar_m), rel=1e-13)
+
+
+@pytest.mark.parametrize("L,periodic,kappa", [(12, True, 2.0), (9, False, 1.0), (10, False, 3.0)])
+def test_set_temperature_equals_a_fresh_chain(L, periodic, kappa):
+    """A new temperature rebuilds exactly the columns a chain created at that
+    temperature has (Eqs. 2-3 at the new beta), and the chain then runs as one that
+    started at the new temperature from the same spins."""
+    import oracle
+
+    a = oracle.OracleChain(oracle.ChainParams(L=L, periodic=periodic, T=1.25, kappa=kappa))
+    a.step(0)
+    a.set_temperature(0.45)
+    b = oracle.OracleChain(oracle.ChainParams(L=L, periodic=periodic, T=0.45, kappa=kappa), init_spins=a.spins)
+    ta, tb = a.tables(), b.tables()
+    for k in ta:
+        np.testing.assert_array_equal(ta[k], tb[k], err_msg=k)
+    for t in range(1, 4):
+        a.step(t)
+        b.step(t)
+    np.testing.assert_array_equal(a.spins, b.spins)
+    with pytest.raises(ValueError):
+        a.set_temperature(0.0)
