@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("J", ctypes.c_double), ("D", ctypes.c_double), ("T", ctypes.c_double),
         ("kappa", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("chain_id", ctypes.c_uint32),
+        ("coloring", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -100,6 +101,9 @@ def lib():
         L.orc_partner.argtypes = [P, ctypes.c_int, ctypes.c_int]; L.orc_partner.restype = ctypes.c_int
         L.orc_reset_counters.argtypes = [P]; L.orc_reset_counters.restype = None
         L.orc_set_temperature.argtypes = [P, ctypes.c_double]; L.orc_set_temperature.restype = ctypes.c_int
+        for name in ("orc_color_rule2", "orc_color_whole_rule2"):
+            getattr(L, name).argtypes = [P, P, ctypes.POINTER(ctypes.c_int64)]
+            getattr(L, name).restype = ctypes.c_int
         L.orc_survival_counts.argtypes = [P, ctypes.c_uint64, ctypes.c_int, P]
         L.orc_survival_counts.restype = None
         L.orc_run_record.argtypes = [P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, P, P]
@@ -137,10 +141,12 @@ class ChainParams:
     n_sw: int = 1
     seed: int = 1
     chain_id: int = 0
+    coloring: int = 0  # 0 KW (2)', 1 checkerboard x KW of the bonds, 2 whole-graph BCR (2)'
 
     def to_c(self) -> Params:
         return Params(self.L, int(self.periodic), self.n_images, self.n_sw, self.J, self.D,
-                      self.T, self.kappa, self.seed & 0xFFFFFFFF, self.chain_id & 0xFFFFFFFF)
+                      self.T, self.kappa, self.seed & 0xFFFFFFFF, self.chain_id & 0xFFFFFFFF,
+                      int(self.coloring), 0)
 
 
 class OracleChain:
@@ -229,6 +235,16 @@ class OracleChain:
 
     def reset_counters(self) -> None:
         lib().orc_reset_counters(self._h)
+
+    def colors_rule2(self, whole: bool = False):
+        """The colouring with the basic step (2) instead of rule (2)': in every KW level,
+        or on the whole graph from the N-colouring (small lattices); (colours, rounds)."""
+        out = np.empty(self.N, np.int32)
+        r = ctypes.c_int64(0)
+        f = lib().orc_color_whole_rule2 if whole else lib().orc_color_rule2
+        if f(self._h, _ptr(out), ctypes.byref(r)) != 0:
+            raise RuntimeError("colouring ran out of colours")
+        return out, int(r.value)
 
     def set_temperature(self, T: float) -> None:
         if lib().orc_set_temperature(self._h, float(T)) != 0:

@@ -44,6 +44,10 @@ typedef struct {
   int32_t L, periodic, n_images, n_sw;
   double J, D, T, kappa;
   uint32_t seed, chain_id;
+  /* colouring of Fig. 1 step (2): 0 KW with rule (2)' on the union graph; 1 the
+   * checkerboard product 2 c + ((x + y) mod 2), c a KW colouring of the bonds alone;
+   * 2 basic colour reduction with rule (2)' on the whole union graph, no KW groups */
+  int32_t coloring, pad;
 } orc_params;
 
 typedef struct {
@@ -373,10 +377,10 @@ int orc_switch(orc_chain* c, uint64_t t) {
   return 0;
 }
 
-/* distinct neighbours of v in the union of the exchange lattice and the surviving
- * bonds; returns the count */
-static int union_neighbours(const orc_chain* c, int v, int32_t* out, int cap) {
-  int nb[4], n = neighbours(c, v, nb), cnt = 0;
+/* distinct neighbours of v in the union of the exchange lattice (with_nn) and the
+ * surviving bonds; returns the count */
+static int graph_neighbours(const orc_chain* c, int v, int32_t* out, int cap, int with_nn) {
+  int nb[4], n = with_nn ? neighbours(c, v, nb) : 0, cnt = 0;
   for (int a = 0; a < n; ++a) {
     int dup = 0;
     for (int b = 0; b < cnt; ++b) dup |= (out[b] == nb[a]);
@@ -395,33 +399,32 @@ static int union_neighbours(const orc_chain* c, int v, int32_t* out, int cap) {
  * colour = site index), so vertex v starts in group v/q with colour v mod q inside
  * it.  Level p unites pairs of groups; the upper half (bit p-1 of v/q set) carries
  * colours q..2q-1 and is reduced back into 0..q-1 by colour-reduction rounds
- * (Sec. 2.3.2, rule (2)'): in a round every pending vertex whose colour exceeds
- * the colour of every pending neighbour of its group takes the smallest colour in
- * 0..q-1 that no neighbour of its group holds.  All decisions of a round read the
- * colours of the previous round (synchronous communication, Sec. 2.3.1). */
-int orc_color(orc_chain* c) {
-  int N = c->N, maxdeg = 0;
+ * (Sec. 2.3.2).  rule 3 is rule (2)': in a round every pending vertex whose colour
+ * exceeds the colour of every pending neighbour of its group takes the smallest colour
+ * in 0..q-1 that no neighbour of its group holds.  rule 2 is the basic step (2): round
+ * r recolours the vertices of colour alpha = 2q - r (alpha runs from 2q-1 down to q,
+ * one colour per round).  All decisions of a round read the colours of the previous
+ * round (synchronous communication, Sec. 2.3.1).  The graph is the union of the
+ * exchange lattice and the bonds (with_nn) or the bonds alone.  Returns -1 when a
+ * palette of q colours does not suffice. */
+static int kw_reduce(orc_chain* c, int q, int with_nn, int rule, int32_t* cur, int64_t* total_rounds,
+                     int32_t* level_rounds, int* levels) {
+  int N = c->N;
   int32_t nbuf[4096];
-  /* the union graph's adjacency, listed once per colouring */
+  /* the graph's adjacency, listed once */
   int32_t* uoff = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N + 1));
   size_t ucap = (size_t)N * 4 + 2 * (size_t)c->n_edges + 1, un = 0;
   int32_t* uadj = (int32_t*)malloc(sizeof(int32_t) * ucap);
   for (int v = 0; v < N; ++v) {
-    int d = union_neighbours(c, v, nbuf, 4096);
-    if (d > maxdeg) maxdeg = d;
+    int d = graph_neighbours(c, v, nbuf, 4096, with_nn);
     uoff[v] = (int32_t)un;
     for (int a = 0; a < d; ++a) uadj[un++] = nbuf[a];
   }
   uoff[N] = (int32_t)un;
-  int q = maxdeg + 1;
-  c->delta_union = maxdeg;
-  c->q = q;
   int groups = (N + q - 1) / q, M = 0;
   while ((1 << M) < groups) ++M;
-  c->M = M;
-  c->kw_rounds = 0;
-  memset(c->kw_rounds_level, 0, 64 * sizeof(int32_t));
-  int32_t* cur = c->color;
+  *levels = M;
+  *total_rounds = 0;
   uint8_t* pend = (uint8_t*)calloc((size_t)N, 1);
   int32_t* plist = (int32_t*)malloc(sizeof(int32_t) * (size_t)N); /* pending vertices */
   int32_t* dec_v = (int32_t*)malloc(sizeof(int32_t) * (size_t)N); /* decisions of a round */
@@ -436,23 +439,27 @@ int orc_color(orc_chain* c) {
       if (pend[v]) { cur[v] += q; plist[npending++] = v; }
     }
     int rounds = 0;
-    while (npending > 0) {
+    /* rule (2)' runs until no vertex is pending; rule (2) runs alpha from 2q-1 down to
+     * q, one colour per round, whether or not a colour class is empty */
+    while (rule == 2 ? rounds < q : npending > 0) {
       ++rounds;
       /* every decision of the round reads the colours and pending marks left by the
        * previous round; they are applied together afterwards */
       int ndec = 0;
+      const int alpha = 2 * q - rounds; /* rule (2): the colour recoloured this round */
       for (int k = 0; k < npending; ++k) {
         int v = plist[k];
         int grp = (v / q) >> p;
-        int localmax = 1;
+        int go = 1;
         memset(used, 0, (size_t)q);
         for (int x = uoff[v]; x < uoff[v + 1]; ++x) {
           int u = uadj[x];
           if (((u / q) >> p) != grp) continue;
-          if (pend[u] && cur[u] > cur[v]) localmax = 0;
+          if (rule == 3 && pend[u] && cur[u] > cur[v]) go = 0;
           if (cur[u] < q) used[cur[u]] = 1;
         }
-        if (!localmax) continue;
+        if (rule == 2) go = (cur[v] == alpha);
+        if (!go) continue;
         int nc = 0;
         while (nc < q && used[nc]) ++nc;
         if (nc == q) { fail = 1; break; }
@@ -470,10 +477,147 @@ int orc_color(orc_chain* c) {
         if (pend[plist[k]]) plist[keep++] = plist[k];
       npending = keep;
     }
-    c->kw_rounds_level[p < 64 ? p : 63] = rounds;
-    c->kw_rounds += rounds;
+    if (npending > 0) fail = 1; /* cannot happen: every pending colour is some alpha */
+    level_rounds[p < 64 ? p : 63] = rounds;
+    *total_rounds += rounds;
   }
   free(uoff); free(uadj); free(pend); free(plist); free(dec_v); free(dec_c); free(used);
+  return fail ? -1 : 0;
+}
+
+/* Basic colour reduction on the whole union graph, no KW groups (Sec. 2.3.2): the
+ * initial colour is the site index, the vertices with colours q..N-1 are pending, and
+ * in every round each pending vertex whose colour exceeds those of all its pending
+ * neighbours takes the smallest colour in 0..q-1 that no neighbour holds (rule (2)');
+ * rounds read the previous round's colours.  Returns -1 when q colours do not suffice. */
+static int bcr_whole(orc_chain* c, int q, int32_t* cur, int64_t* rounds_out) {
+  int N = c->N;
+  int32_t nbuf[4096];
+  int32_t* uoff = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N + 1));
+  size_t ucap = (size_t)N * 4 + 2 * (size_t)c->n_edges + 1, un = 0;
+  int32_t* uadj = (int32_t*)malloc(sizeof(int32_t) * ucap);
+  for (int v = 0; v < N; ++v) {
+    int d = graph_neighbours(c, v, nbuf, 4096, 1);
+    uoff[v] = (int32_t)un;
+    for (int a = 0; a < d; ++a) uadj[un++] = nbuf[a];
+  }
+  uoff[N] = (int32_t)un;
+  int32_t* plist = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t* dec_v = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t* dec_c = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  uint8_t* used = (uint8_t*)malloc((size_t)q);
+  int npending = 0, fail = 0;
+  int64_t rounds = 0;
+  for (int v = 0; v < N; ++v) {
+    cur[v] = v;
+    if (v >= q) plist[npending++] = v;
+  }
+  while (npending > 0 && !fail) {
+    ++rounds;
+    int ndec = 0;
+    for (int k = 0; k < npending; ++k) {
+      int v = plist[k], localmax = 1;
+      memset(used, 0, (size_t)q);
+      for (int x = uoff[v]; x < uoff[v + 1]; ++x) {
+        int u = uadj[x];
+        if (cur[u] >= q && cur[u] > cur[v]) localmax = 0;
+        if (cur[u] < q) used[cur[u]] = 1;
+      }
+      if (!localmax) continue;
+      int nc = 0;
+      while (nc < q && used[nc]) ++nc;
+      if (nc == q) { fail = 1; break; }
+      dec_v[ndec] = v;
+      dec_c[ndec] = nc;
+      ++ndec;
+    }
+    for (int k = 0; k < ndec; ++k) cur[dec_v[k]] = dec_c[k];
+    int keep = 0;
+    for (int k = 0; k < npending; ++k)
+      if (cur[plist[k]] >= q) plist[keep++] = plist[k];
+    npending = keep;
+  }
+  *rounds_out = rounds;
+  free(uoff); free(uadj); free(plist); free(dec_v); free(dec_c); free(used);
+  return fail ? -1 : 0;
+}
+
+/* maximum degree of the union graph (with_nn) or of the bonds alone */
+static int max_degree(const orc_chain* c, int with_nn) {
+  int32_t nbuf[4096];
+  int maxdeg = 0;
+  for (int v = 0; v < c->N; ++v) {
+    int d = graph_neighbours(c, v, nbuf, 4096, with_nn);
+    if (d > maxdeg) maxdeg = d;
+  }
+  return maxdeg;
+}
+
+int orc_color(orc_chain* c) {
+  int N = c->N;
+  c->delta_union = max_degree(c, 1);
+  memset(c->kw_rounds_level, 0, 64 * sizeof(int32_t));
+  int rc = 0;
+  if (c->p.coloring == 1) {
+    /* checkerboard product: a KW colouring c' of the bonds alone with
+     * q = max(Delta_bonds + 1, 2), then colour 2 c' + ((x + y) mod 2): bond partners
+     * differ in c', lattice neighbours in the parity */
+    int q = max_degree(c, 0) + 1;
+    if (q < 2) q = 2;
+    c->q = q;
+    int M = 0;
+    rc = kw_reduce(c, q, 0, 3, c->color, &c->kw_rounds, c->kw_rounds_level, &M);
+    c->M = M;
+    for (int v = 0; v < N; ++v) c->color[v] = 2 * c->color[v] + ((v % c->L + v / c->L) & 1);
+  } else if (c->p.coloring == 2) {
+    c->q = c->delta_union + 1;
+    c->M = 1;
+    rc = bcr_whole(c, c->q, c->color, &c->kw_rounds);
+    c->kw_rounds_level[1] = (int32_t)c->kw_rounds;
+  } else {
+    c->q = c->delta_union + 1;
+    int M = 0;
+    rc = kw_reduce(c, c->q, 1, 3, c->color, &c->kw_rounds, c->kw_rounds_level, &M);
+    c->M = M;
+  }
+  return rc;
+}
+
+/* Test helper: the KW colouring of the union graph with the basic step (2) in every
+ * level instead of rule (2)' (colours into out[N], rounds into *rounds). */
+int orc_color_rule2(orc_chain* c, int32_t* out, int64_t* rounds) {
+  int32_t lv[64];
+  int M = 0;
+  return kw_reduce(c, max_degree(c, 1) + 1, 1, 2, out, rounds, lv, &M);
+}
+
+/* Test helper: basic colour reduction with step (2) on the whole union graph from the
+ * N-colouring (N - q rounds; small lattices only). */
+int orc_color_whole_rule2(orc_chain* c, int32_t* out, int64_t* rounds) {
+  int N = c->N, q = max_degree(c, 1) + 1;
+  int32_t nbuf[4096];
+  uint8_t* used = (uint8_t*)malloc((size_t)q);
+  int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int fail = 0;
+  for (int v = 0; v < N; ++v) out[v] = v;
+  *rounds = 0;
+  for (int alpha = N - 1; alpha >= q && !fail; --alpha) { /* one colour per round */
+    ++*rounds;
+    memcpy(nxt, out, sizeof(int32_t) * (size_t)N);
+    for (int v = 0; v < N; ++v) {
+      if (out[v] != alpha) continue;
+      int d = graph_neighbours(c, v, nbuf, 4096, 1);
+      memset(used, 0, (size_t)q);
+      for (int a = 0; a < d; ++a)
+        if (out[nbuf[a]] < q) used[out[nbuf[a]]] = 1;
+      int nc = 0;
+      while (nc < q && used[nc]) ++nc;
+      if (nc == q) { fail = 1; break; }
+      nxt[v] = nc;
+    }
+    memcpy(out, nxt, sizeof(int32_t) * (size_t)N);
+  }
+  free(used); free(nxt);
   return fail ? -1 : 0;
 }
 

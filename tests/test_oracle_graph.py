@@ -163,3 +163,100 @@ def test_kw_single_group():
     if o["q"] >= 4:
         assert o["kw_levels"] == 0
         np.testing.assert_array_equal(c.colors(), np.arange(4))
+
+
+# ----------------------------------------------------------------- colouring variants
+# Sec. 2.3.2 gives two rules for one round of basic colour reduction: step (2)
+# recolours the vertices of the largest colour alpha, step (2)' every vertex whose
+# colour is locally maximal.  In both, a pending vertex recolours only after all of its
+# pending neighbours of larger colour have, and it then sees their new colours, so the
+# two rules yield the same colours and differ only in the number of rounds.
+
+@pytest.mark.parametrize("L,periodic,T,kappa", [(12, True, 1.0, 2.0), (10, False, 0.8, 1.0),
+                                                (16, True, 0.5, 3.0)])
+def test_kw_rule2_gives_the_same_colours_in_q_rounds_per_level(L, periodic, T, kappa):
+    c = OracleChain(ChainParams(L=L, periodic=periodic, T=T, kappa=kappa))
+    c.step(0)
+    c.switch(1)
+    c.color()
+    o = c.observables(dipolar="none")
+    col2, r2 = c.colors_rule2()
+    np.testing.assert_array_equal(col2, c.colors())
+    q, M = o["q"], o["kw_levels"]
+    assert r2 == q * M, "step (2): alpha runs from 2q-1 down to q in every level (Eq. 5)"
+    assert o["kw_rounds"] <= r2
+
+
+def greedy_decreasing(adj, N, q):
+    """Sequential greedy colouring in decreasing vertex order: vertices 0..q-1 keep
+    their index as colour, every other vertex takes the smallest colour unused by its
+    neighbours (textbook first-fit)."""
+    col = list(range(N))
+    for v in range(N - 1, q - 1, -1):
+        used = {col[u] for u in adj[v] if col[u] < q}
+        col[v] = next(k for k in range(q) if k not in used)
+    return col
+
+
+def decreasing_depth(adj, N, q):
+    """Longest chain of pending vertices (index >= q) joined by edges along which the
+    index increases: the number of synchronous rounds of rule (2)'."""
+    depth = [0] * N
+    best = 0
+    for v in range(N - 1, q - 1, -1):
+        d = 1 + max([depth[u] for u in adj[v] if u > v and u >= q], default=0)
+        depth[v] = d
+        best = max(best, d)
+    return best
+
+
+@pytest.mark.parametrize("L,periodic,T,kappa", [(8, True, 1.0, 2.0), (9, False, 0.7, 1.0),
+                                                (16, True, 1.2, 1.0), (20, False, 0.9, 2.0)])
+def test_whole_graph_reduction_is_first_fit_in_decreasing_order(L, periodic, T, kappa):
+    """Basic colour reduction on the whole union graph (no KW groups) with rule (2)'
+    gives the first-fit colouring in decreasing site order, in as many rounds as the
+    longest increasing-index chain of pending vertices; step (2) gives the same colours
+    in N - (Delta+1) rounds."""
+    c = OracleChain(ChainParams(L=L, periodic=periodic, T=T, kappa=kappa, coloring=2))
+    c.step(0)
+    c.switch(1)
+    c.color()
+    o = c.observables(dipolar="none")
+    adj = union_adjacency(c)
+    delta = max(len(a) for a in adj)
+    q = delta + 1
+    assert o["q"] == q and o["kw_levels"] == 1
+    colours = c.colors()
+    np.testing.assert_array_equal(colours, greedy_decreasing(adj, c.N, q))
+    assert o["kw_rounds"] == decreasing_depth(adj, c.N, q)
+    assert all(colours[v] != colours[u] for v in range(c.N) for u in adj[v])
+    if c.N <= 100:
+        col2, r2 = c.colors_rule2(whole=True)
+        np.testing.assert_array_equal(col2, colours)
+        assert r2 == c.N - q
+
+
+@pytest.mark.parametrize("L,periodic,T,kappa", [(16, True, 1.0, 2.0), (12, False, 0.6, 3.0),
+                                                (32, True, 1.2, 1.0)])
+def test_checkerboard_product_colouring(L, periodic, T, kappa):
+    """Colour 2 c + ((x + y) mod 2), c a KW colouring of the bonds alone with
+    q = max(Delta_bonds + 1, 2): proper on the union graph, below 2 q, and c equals a
+    KW colouring of the bond graph by the paper transcription."""
+    c = OracleChain(ChainParams(L=L, periodic=periodic, T=T, kappa=kappa, coloring=1))
+    c.step(0)
+    c.switch(1)
+    c.color()
+    o = c.observables(dipolar="none")
+    rp, col, _ = c.csr()
+    bonds = [set(int(u) for u in col[rp[v]:rp[v + 1]]) for v in range(c.N)]
+    q = max(max(len(b) for b in bonds) + 1, 2)
+    assert o["q"] == q
+    colours = c.colors()
+    assert colours.max() < 2 * q and colours.min() >= 0
+    adj = union_adjacency(c)
+    assert all(colours[v] != colours[u] for v in range(c.N) for u in adj[v])
+    par = (np.arange(c.N) % L + np.arange(c.N) // L) % 2
+    np.testing.assert_array_equal(colours % 2, par)
+    ref, M, rounds = paper_kw(bonds, c.N, q - 1)
+    np.testing.assert_array_equal(colours // 2, np.asarray(ref))
+    assert o["kw_levels"] == M
