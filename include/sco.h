@@ -242,6 +242,20 @@ int sco_trace_read(sco_ctx* ctx, int32_t* ids, double* us, int max, int* n);
  * blocks, 28672-site tiles); blocks must be 1 .. that limit and tile_limit 64 .. 28672,
  * else SCO_EINVAL. */
 int sco_set_schedule(sco_ctx* ctx, int blocks, int tile_limit);
+
+/* Colouring of step (2) for the steps that follow (every chain of the context; each
+ * colouring changes the sweep order and so the chain, and the oracle takes the same
+ * mode):
+ *   0  Kuhn-Wattenhofer colour reduction of the union graph, rule (2)' in every level
+ *      (Sec. 2.3.2-2.3.3; the default);
+ *   1  the checkerboard product 2 c + ((x + y) mod 2), c a KW colouring of the bonds
+ *      alone with q = max(Delta_bonds + 1, 2) (2 q colours; SCO_EPALETTE above 128);
+ *   2  basic colour reduction with rule (2)' on the whole union graph, without KW groups
+ *      (Sec. 2.3.2): first-fit in decreasing site order, one round per level of the
+ *      increasing-index dependence (kw_levels 1, kw_rounds the rounds).
+ * Rule (2) in place of (2)' gives the same colours in (Delta + 1) M rounds (Eq. 5), or
+ * N - Delta - 1 without KW.  SCO_EINVAL for another mode. */
+int sco_set_coloring(sco_ctx* ctx, int mode);
 int sco_get_schedule(sco_ctx* ctx, int* blocks, int* tile_limit);
 
 /* Autotuner: times trial_steps (1 .. 1000) full steps for each candidate schedule

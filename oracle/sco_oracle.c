@@ -628,8 +628,10 @@ int orc_color_whole_rule2(orc_chain* c, int32_t* out, int64_t* rounds) {
  * infinite pseudo-energy, so a spin carrying a surviving bond never flips. */
 int orc_sweep(orc_chain* c, uint64_t t, int n_sw) {
   int N = c->N;
+  /* every colour class of the palette: q colours, 2 q for the checkerboard product */
+  const int np = c->p.coloring == 1 ? 2 * c->q : c->q;
   for (int s = 0; s < n_sw; ++s)
-    for (int col = 0; col < c->q; ++col)
+    for (int col = 0; col < np; ++col)
       for (int v = 0; v < N; ++v) {
         if (c->color[v] != col) continue;
         c->attempts++;
@@ -694,9 +696,11 @@ void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
   }
   int colors_used = 0;
   if (c->q > 0) {
-    uint8_t* seen = (uint8_t*)calloc((size_t)c->q, 1);
-    for (int v = 0; v < N; ++v) if (c->color[v] >= 0 && c->color[v] < c->q) seen[c->color[v]] = 1;
-    for (int a = 0; a < c->q; ++a) colors_used += seen[a];
+    /* the palette: q colours, 2 q for the checkerboard product */
+    const int np = c->p.coloring == 1 ? 2 * c->q : c->q;
+    uint8_t* seen = (uint8_t*)calloc((size_t)np, 1);
+    for (int v = 0; v < N; ++v) if (c->color[v] >= 0 && c->color[v] < np) seen[c->color[v]] = 1;
+    for (int a = 0; a < np; ++a) colors_used += seen[a];
     free(seen);
   }
   o->E_exchange = -c->p.J * (double)ex;

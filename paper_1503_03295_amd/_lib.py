@@ -16,7 +16,7 @@ EXPORTS = [
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
     "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags", "sco_counters", "sco_run_noalloc", "sco_run_graph",
-    "sco_set_temperature", "sco_anneal",
+    "sco_set_temperature", "sco_anneal", "sco_set_coloring",
 ]
 
 
@@ -94,6 +94,7 @@ def lib():
         "sco_run": ([P, u64, i32], i32),
         "sco_run_graph": ([P, u64, i32], i32),
         "sco_set_temperature": ([P, i32, ctypes.c_double], i32),
+        "sco_set_coloring": ([P, i32], i32),
         "sco_anneal": ([P, ctypes.POINTER(ctypes.c_double), i32, i32, i32, u64, ctypes.POINTER(StageC)], i32),
         "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_counters": ([P, ctypes.POINTER(ObsC)], i32),

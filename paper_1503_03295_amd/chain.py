@@ -198,6 +198,11 @@ class SCO:
     def set_schedule(self, blocks: int = 0, tile_limit: int = 0) -> None:
         check(lib().sco_set_schedule(self._h, int(blocks), int(tile_limit)), "sco_set_schedule", self._h)
 
+    def set_coloring(self, mode: int) -> None:
+        """0 KW rule (2)' (default), 1 checkerboard x KW of the bonds, 2 whole-graph
+        basic colour reduction (2)'."""
+        check(lib().sco_set_coloring(self._h, int(mode)), "sco_set_coloring", self._h)
+
     def schedule(self) -> tuple[int, int]:
         b, t = ctypes.c_int(), ctypes.c_int()
         check(lib().sco_get_schedule(self._h, ctypes.byref(b), ctypes.byref(t)), "sco_get_schedule", self._h)

@@ -816,6 +816,13 @@ int sco_set_schedule(sco_ctx* c, int blocks, int tile_limit) {
   return SCO_OK;
 }
 
+int sco_set_coloring(sco_ctx* c, int mode) {
+  if (!c || mode < SCO_COLOR_KW || mode > SCO_COLOR_BCR) return SCO_EINVAL;
+  c->args.coloring = mode;
+  if (c->graph_state == 2) c->graph_state = 1;  // the colouring of the current graph is stale
+  return SCO_OK;
+}
+
 int sco_get_schedule(sco_ctx* c, int* blocks, int* tile_limit) {
   if (!c) return SCO_EINVAL;
   if (blocks) *blocks = c->blocks;

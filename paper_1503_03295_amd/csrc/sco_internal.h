@@ -25,6 +25,11 @@ enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4 };
 
 enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4, SCO_FLAG_STATE = 8 };
 
+// colouring of step (2): KW with rule (2)' on the union graph; the checkerboard product
+// 2 c + ((x + y) mod 2) of a KW colouring c of the bonds alone; basic colour reduction
+// with rule (2)' on the whole union graph (no KW groups)
+enum { SCO_COLOR_KW = 0, SCO_COLOR_CHECKER = 1, SCO_COLOR_BCR = 2 };
+
 // Immutable per-chain description (device copy written once by sco_init).
 struct ChainDesc {
   int32_t L, N, K, periodic;
@@ -73,7 +78,8 @@ struct SyncWords {
   uint32_t qmax, mmax;
   uint32_t graph_valid;  // 1 once a switching phase completed (0 while one runs)
   uint32_t color_valid;  // 1 once a colouring of the current graph completed
-  uint32_t pad2[26];
+  uint32_t fcount[3];    // frontier sizes of the whole-graph colour reduction (rotating)
+  uint32_t pad2[23];
 };
 
 // Arguments of the persistent step kernel (all device pointers into the workspace).
@@ -103,6 +109,7 @@ struct StepArgs {
   int32_t nsw_max;
   uint32_t step;
   int32_t tile_limit;     // sites of a KW tile, <= SCO_TILE_MAX (a schedule choice)
+  int32_t coloring;       // SCO_COLOR_KW, SCO_COLOR_CHECKER or SCO_COLOR_BCR
 };
 
 #define SCO_TRACE_SLOTS 512

@@ -1224,11 +1224,15 @@ __device__ __forceinline__ void kw_setup(const StepArgs& a, KwShared& ks) {
   // every block computes the same per-chain parameters (Delta is final here)
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
     const ChainDesc& d = a.cd[c];
-    // every site has a nearest neighbour, so q >= 2 (the tile divisions rely on it)
-    int q = max(a.st[c].delta_union + 1, 2);
-    if (q > SCO_MAXQ) {
+    // every site has a nearest neighbour, so q >= 2 (the tile divisions rely on it);
+    // the checkerboard product colours the bonds alone (palette of at least 2) and
+    // doubles the colours, which must still fit a byte
+    const bool checker = a.coloring == SCO_COLOR_CHECKER;
+    int q = max((checker ? a.st[c].delta_sco : a.st[c].delta_union) + 1, 2);
+    const int qlim = checker ? (SCO_MAXQ + 1) / 2 : SCO_MAXQ;
+    if (q > qlim) {
       set_flag(a.sync, SCO_FLAG_PALETTE);
-      q = SCO_MAXQ;
+      q = qlim;
     }
     const int groups = (d.N + q - 1) / q;
     int M = 0;
@@ -1247,8 +1251,8 @@ __device__ __forceinline__ void kw_setup(const StepArgs& a, KwShared& ks) {
     k.inv_q = 1.0 / q;
     if (blockIdx.x == 0) {
       a.st[c].q = q;
-      a.st[c].M = M;
-      a.st[c].P = P;
+      a.st[c].M = a.coloring == SCO_COLOR_BCR ? 1 : M;  // one whole-graph reduction
+      a.st[c].P = a.coloring == SCO_COLOR_BCR ? 0 : P;
     }
   }
   __syncthreads();
@@ -1268,7 +1272,8 @@ __device__ __forceinline__ void kw_setup(const StepArgs& a, KwShared& ks) {
     ks.mmax = mmax;
     ks.pmin = pmin;
     if (blockIdx.x == 0) {
-      a.sync->qmax = static_cast<uint32_t>(qmax);
+      // the sweep's colour classes
+      a.sync->qmax = static_cast<uint32_t>(a.coloring == SCO_COLOR_CHECKER ? 2 * qmax : qmax);
       a.sync->mmax = static_cast<uint32_t>(mmax);
     }
   }
@@ -1325,6 +1330,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
   const uint32_t lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int tid = static_cast<int>(threadIdx.x);
+  const bool checker = a.coloring == SCO_COLOR_CHECKER;
   // rank of a site with in-tile bonds among those of the tile
   auto bond_rank = [&](int i) {
     return static_cast<int>(t_brank[i >> 5]) + __popc(t_bmask[i >> 5] & ((1u << (i & 31)) - 1u));
@@ -1547,8 +1553,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
                 const int t = x0 + i, dy = div16(t, mL);
                 int nb[4];
                 nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
+                // the checkerboard product colours the bonds alone
 #pragma unroll
-                for (int u = 0; u < 4; ++u) jt[u] = nb[u] >= 0 ? nb[u] - v0 : -1;
+                for (int u = 0; u < 4; ++u) jt[u] = nb[u] >= 0 && !checker ? nb[u] - v0 : -1;
                 e0 = e1 = g0 = g1 = 0;
                 const uint32_t mw = t_bmask[i >> 5];
                 if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
@@ -1632,7 +1639,12 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     const uint32_t tag = static_cast<uint32_t>(P) << 18;
     for (int i = threadIdx.x; i < n; i += kBlock) {
       const uint32_t col = t_cr[i] & 0xFFu;
-      a.color[gt0 + i] = static_cast<uint16_t>(col);
+      uint32_t out = col;
+      if (checker) {  // 2 c + ((x + y) mod 2)
+        const int t = x0 + i, dy = div16(t, mL);
+        out = 2u * col + static_cast<uint32_t>((t - dy * L + y0 + dy) & 1);
+      }
+      a.color[gt0 + i] = static_cast<uint16_t>(out);
       a.kw_word[gt0 + i] = tag | col;
     }
     __syncthreads();
@@ -1842,6 +1854,7 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
               g = vb + v;
               const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
               nn_sites(x, y, K.L, K.periodic, nbs);
+              if (a.coloring == SCO_COLOR_CHECKER) nbs[0] = nbs[1] = nbs[2] = nbs[3] = -1;
               // a first read may return an older value of a word (a copy this XCD's L2
               // still holds): an older value shows a higher-class neighbour as
               // undecided, so the site only waits and re-reads with read-modify-writes;
@@ -1947,8 +1960,150 @@ __device__ __forceinline__ void phase_colour_fill(const StepArgs& a) {
   const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
   const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
   const int64_t r1 = min(r0 + S, a.G);
-  for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) a.color[g] = static_cast<uint16_t>(a.kw_word[g] & 0x1FFu);
+  if (a.coloring == SCO_COLOR_CHECKER) {  // 2 c + ((x + y) mod 2)
+    for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) {
+      const ChainDesc& d = a.cd[a.chunk_chain[g >> SCO_CHUNK_SHIFT]];
+      const int v = static_cast<int>(g - d.vbase);
+      const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
+      a.color[g] = static_cast<uint16_t>(2u * (a.kw_word[g] & 0x1FFu) + static_cast<uint32_t>((x + y) & 1));
+    }
+  } else {
+    for (int64_t g = r0 + threadIdx.x; g < r1; g += kBlock) a.color[g] = static_cast<uint16_t>(a.kw_word[g] & 0x1FFu);
+  }
   __syncthreads();
+}
+
+// Basic colour reduction with rule (2)' on the whole union graph (no KW groups,
+// Sec. 2.3.2): the initial colour of a site is its index v, the sites v >= q of every
+// chain are pending, and a pending site recolours once every pending neighbour of larger
+// colour (index) has, taking the smallest colour in 0..q-1 that no neighbour holds.
+// The synchronous rounds are run level by level of that dependence: dep[v] counts the
+// pending neighbours above v; the sites at zero form round 1, and every decision
+// decrements the counts of its pending neighbours below it, queueing those that reach
+// zero for the next round.  A site decides in round 1 + max over its pending
+// neighbours above it, the round of the Jacobi iteration, and sees exactly their new
+// colours, so the colours are those of the rounds.  dep lives in `fill`, the two
+// rotating frontier lists in `rec`, their sizes in sync->fcount.  Returns false when
+// the launch must end.
+__device__ __forceinline__ bool phase_color_bcr(const StepArgs& a, const KwShared& ks, int32_t* lds) {
+  const int tid = static_cast<int>(threadIdx.x);
+  const uint32_t lane = lane_id();
+  int32_t* const dep = a.fill;
+  int32_t* const lists = reinterpret_cast<int32_t*>(a.rec);  // [0, G) and [G, 2 G)
+  int32_t* const rnd = lds;  // per chain: the last round in which one of its sites decided
+  for (int c = tid; c < a.n_chains; c += kBlock) rnd[c] = 0;
+  // the union neighbours of global site g (chain c, local v): the lattice neighbours,
+  // then the bond partners that are not among them; f(u) for each
+  auto for_union = [&](int c, int v, int64_t g, auto&& f) __attribute__((always_inline)) {
+    const KwChain& K = ks.kc[c];
+    const int y = idiv_fp(v, K.inv_L), x = v - y * K.L;
+    int nb[4];
+    nn_sites(x, y, K.L, K.periodic, nb);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (nb[t] >= 0) f(nb[t]);
+    int r0 = a.row_ptr[g], r1 = a.row_ptr[g + 1];
+    row_checked(a, r0, r1);
+    for (int e = r0; e < r1; ++e) {
+      const int u = a.col[e] - static_cast<int32_t>(K.vbase);
+      if (u != nb[0] && u != nb[1] && u != nb[2] && u != nb[3]) f(u);
+    }
+  };
+  // appends site g to list `lst` (one atomic per wave); every lane of the wave calls it
+  auto append = [&](bool on, int32_t g, int32_t* lst, uint32_t* cnt) {
+    const uint64_t m = __ballot(on);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    uint32_t base = 0;
+    if (static_cast<int>(lane) == leader)
+      base = __hip_atomic_fetch_add(cnt, static_cast<uint32_t>(__popcll(m)), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, leader);
+    if (on) lst[base + __popcll(m & ((1ull << lane) - 1ull))] = g;
+  };
+  if (blockIdx.x == 0 && tid < 3) a.sync->fcount[tid] = 0u;
+  if (!grid_barrier(a.sync)) return false;
+  // initial colours and dependence counts; the sites without a pending neighbour above
+  // them form the first frontier (list 1, size fcount[1])
+  for (int64_t gb = static_cast<int64_t>(blockIdx.x) * kBlock; gb < a.G; gb += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t g = gb + tid;
+    const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+    const KwChain& K = ks.kc[c];
+    const int v = static_cast<int>(g - K.vbase);
+    bool ready = false;
+    if (v < K.N) {
+      if (v < K.q) {
+        a.color[g] = static_cast<uint16_t>(v);
+      } else {
+        a.color[g] = 0xFFFFu;
+        int n_up = 0;
+        for_union(c, v, g, [&](int u) { n_up += (u > v) ? 1 : 0; });
+        dep[g] = n_up;
+        ready = n_up == 0;
+      }
+    }
+    append(ready, static_cast<int32_t>(g), lists + a.G, &a.sync->fcount[1]);
+  }
+  for (int r = 1;; ++r) {
+    if (!grid_barrier(a.sync)) return false;
+    const uint32_t nf = ld_poll(&a.sync->fcount[r % 3]);
+    if (nf == 0) break;
+    if (blockIdx.x == 0 && tid == 0) a.sync->fcount[(r + 2) % 3] = 0u;  // round r-1's, read by nobody now
+    const int32_t* cur = lists + ((r & 1) ? a.G : 0);
+    int32_t* nxt = lists + ((r & 1) ? 0 : a.G);
+    uint32_t* ncnt = &a.sync->fcount[(r + 1) % 3];
+    const uint32_t k0 = static_cast<uint32_t>(static_cast<uint64_t>(nf) * blockIdx.x / gridDim.x);
+    const uint32_t k1 = static_cast<uint32_t>(static_cast<uint64_t>(nf) * (blockIdx.x + 1) / gridDim.x);
+    for (uint32_t kb = k0; kb < k1; kb += kBlock) {
+      const uint32_t k = kb + static_cast<uint32_t>(tid);
+      const bool have = k < k1;
+      int c = 0, v = 0;
+      int64_t g = 0;
+      if (have) {
+        g = cur[k];
+        c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+        v = static_cast<int>(g - ks.kc[c].vbase);
+        const int q = ks.kc[c].q;
+        ColorSet taken;
+        for_union(c, v, g, [&](int u) {
+          const int cu = a.color[ks.kc[c].vbase + u];
+          if (cu < q) taken.add(cu);
+        });
+        int nc = taken.first_free();
+        if (nc >= q) {
+          set_flag(a.sync, SCO_FLAG_PALETTE);
+          nc = q - 1;
+        }
+        a.color[g] = static_cast<uint16_t>(nc);
+        atomicMax(&rnd[c], r);
+      }
+      // release the pending neighbours below: those whose count reaches zero join the
+      // next round (at most 4 + the row's bonds per site; one wave-wide append each)
+      int deg = 0;
+      if (have) for_union(c, v, g, [&](int) { ++deg; });
+      const int dmax = wave_max(deg);
+      for (int e = 0; e < dmax; ++e) {
+        int u = -1;
+        if (have && e < deg) {
+          int i = 0;
+          for_union(c, v, g, [&](int w) {
+            if (i++ == e) u = w;
+          });
+        }
+        bool ready = false;
+        int64_t gu = 0;
+        if (u >= 0 && u < v && u >= ks.kc[c].q) {
+          gu = ks.kc[c].vbase + u;
+          ready = atomicSub(&dep[gu], 1) == 1;
+        }
+        append(ready, static_cast<int32_t>(gu), nxt, ncnt);
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < a.n_chains; c += kBlock)
+    if (rnd[c] > 0) atomicMax(&a.st[c].kw_rounds[1], rnd[c]);
+  return true;
 }
 
 // =================================================================== step (3)
@@ -2411,12 +2566,17 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     }
     mark(a.trace, 10);
     kw_setup(a, ks);
-    phase_kw_local(a, ks, lds.tile);
-    mark(a.trace, 11);
-    if (!grid_barrier(a.sync)) return false;
-    // the global levels end with a full barrier (none when every level ran in tiles)
-    if (!phase_kw_global(a, ks, lds.list)) return false;
-    if (ks.mmax > ks.pmin) phase_colour_fill(a);
+    if (a.coloring == SCO_COLOR_BCR) {
+      // ends with the barrier that finds the last frontier empty
+      if (!phase_color_bcr(a, ks, lds.list)) return false;
+    } else {
+      phase_kw_local(a, ks, lds.tile);
+      mark(a.trace, 11);
+      if (!grid_barrier(a.sync)) return false;
+      // the global levels end with a full barrier (none when every level ran in tiles)
+      if (!phase_kw_global(a, ks, lds.list)) return false;
+      if (ks.mmax > ks.pmin) phase_colour_fill(a);
+    }
     mark(a.trace, 12);
     if (lead) a.sync->color_valid = 1;
   }

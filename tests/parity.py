@@ -24,14 +24,14 @@ def log(msg: str) -> None:
 
 
 def oracle_params(p: dict) -> oracle.ChainParams:
-    keys = ("L", "periodic", "T", "J", "D", "kappa", "n_images", "n_sw", "seed", "chain_id")
+    keys = ("L", "periodic", "T", "J", "D", "kappa", "n_images", "n_sw", "seed", "chain_id", "coloring")
     return oracle.ChainParams(**{k: p[k] for k in keys if k in p})
 
 
 def gpu_params(p: dict):
     from paper_1503_03295_amd import ChainParams
 
-    return ChainParams(**p)
+    return ChainParams(**{k: v for k, v in p.items() if k != "coloring"})
 
 
 def compare_state(gpu, ref: oracle.OracleChain, chain: int, what: str, graph: bool = True) -> list[str]:
@@ -60,6 +60,9 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
     gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
     if schedule is not None:
         gpu.set_schedule(*schedule)
+    modes = {p.get("coloring", 0) for p in params}
+    assert len(modes) == 1, "one colouring mode per context"
+    gpu.set_coloring(modes.pop())
     refs = [oracle.OracleChain(oracle_params(p)) for p in params]
     tolerated = 0
     for c, r in enumerate(refs):
