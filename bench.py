@@ -3,12 +3,14 @@
 
 A step is one full pass of the method over the chain: switching of every dipolar
 bond + bond-graph assembly, Kuhn-Wattenhofer colouring + colour bucketing, and n_sw
-colour-ordered Metropolis sweeps.  `value` = spin-update attempts per second over
-the timed steps (N * n_sw per step), inputs resident in HBM, HIP events on the
-library's stream.  A second, untimed-for-`value` pass runs the three phases as
-separate launches to time each one; the slowest phase is reported against the HBM
-roofline with its algorithmic bytes.  The CPU reference is timed on a short sample
-of the same chain (single host thread).
+colour-ordered Metropolis sweeps, all in one persistent kernel launch (k_step<7u>).
+`value` = spin-update attempts per second over the timed steps (N * n_sw per step),
+the steps replayed as one HIP graph, inputs resident in HBM, HIP events on the
+library's stream.  `roofline` puts that kernel's algorithmic bytes per launch over
+its measured time against the HBM peak.  Extra legs: the three phases as separate
+launches, n_sw = 100, the 64-chain batch, the 9-chain mixed-precision workload (FP64
+vs FP32 + recheck), the annealing schedule and the colouring variants.  The CPU
+oracle is timed on a short sample of the same chain (one host thread).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -95,16 +97,86 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def time_steps(sco, first, steps, torch):
-    """ms per step of `steps` full steps (HIP events on the library's stream)."""
+def time_steps(sco, first, steps, torch, graph=True):
+    """ms per step of `steps` full steps (HIP events on the library's stream), as one
+    HIP-graph replay (graph) or as plain launches."""
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(sco.stream)
-    sco.run(first, steps)
+    (sco.run_graph if graph else sco.run)(first, steps)
     e1.record(sco.stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def host_cpu():
+    """The host's logical CPUs and CPU model (for the oracle's timing)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def anneal_leg(torch, SCO, ChainParams, L=512):
+    """The cooling protocol of Sec. 3.1: 1.25 -> 0.05 in steps of 0.05, n_sw = 100, one
+    equilibration and one measured step per temperature, one chain."""
+    import workloads
+
+    temps = [round(1.25 - 0.05 * k, 10) for k in range(25)]
+    p = dict(workloads.chain(L, True, temps[0], 1.0, n_sw=100), edge_factor=32)
+    sco = SCO([ChainParams(**p)], device="cuda:0")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sco.stream)
+    stages = sco.anneal(temps, 1, 1)
+    e1.record(sco.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    steps = 2 * len(temps)
+    pick = {f"{s[0]['T']:.2f}": {k: s[0][k] for k in ("k_mean", "delta_sco_mean", "delta_union_mean", "abs_m",
+                                                       "acceptance")}
+            for s in stages if round(s[0]["T"], 2) in (1.25, 0.45, 0.05)}
+    sco.close()
+    out = {"L": L, "stages": len(temps), "steps": steps, "n_sw": 100, "ms_total": ms,
+           "attempts_per_s": L * L * 100 * steps / (ms / 1e3), "table1_like": pick}
+    progress(f"anneal L={L}: {ms:.1f} ms for {steps} steps; {pick}")
+    return out
+
+
+def coloring_leg(torch, SCO, ChainParams, params, steps=3):
+    """The colouring variants on the headline chain: KW rule (2)', the checkerboard
+    product of a KW colouring of the bonds, and whole-graph basic colour reduction."""
+    out = {}
+    for mode, name in ((0, "kw"), (1, "checkerboard_product"), (2, "whole_graph_bcr")):
+        sco = SCO([ChainParams(**params)], device="cuda:0")
+        sco.set_coloring(mode)
+        # the whole-graph reduction takes of the order of a million rounds at L = 2304:
+        # one timed step, no warm-up
+        warm, n = (2, steps) if mode != 2 else (0, 1)
+        sco.run(0, warm)
+        ms = time_steps(sco, warm, n, torch)
+        t = warm + n
+        sco.switch(t)
+        sco.color()
+        sco.sweep(t, params["n_sw"])
+        ph = sco.phase_times()
+        o = sco.counters()[0]
+        out[name] = {"ms_per_step": ms, "phase_ms": {"switch": ph[0], "color": ph[1], "sweep": ph[2]},
+                     "kw_levels": o["kw_levels"], "kw_rounds": o["kw_rounds"], "q": o["q"],
+                     "colors_used": o["colors_used"]}
+        if mode == 0:
+            out[name]["rounds_rule2_eq5"] = o["q"] * o["kw_levels"]
+        progress(f"colouring {name}: {ms:.3f} ms/step, colour {ph[1]:.3f} ms, rounds {o['kw_rounds']}")
+        sco.close()
+    return out
 
 
 def workload_leg(name, params, steps, torch, SCO, ChainParams, autotune=True):
@@ -113,10 +185,11 @@ def workload_leg(name, params, steps, torch, SCO, ChainParams, autotune=True):
     sched = sco.autotune(2) if autotune else None
     sco.run(0, 2)
     ms = time_steps(sco, 2, steps, torch)
+    ms_plain = time_steps(sco, 2 + steps, steps, torch, graph=False)
     obs = sco.observables()
     spins = sum(p["L"] ** 2 for p in params)
     attempts = sum(p["L"] ** 2 * p["n_sw"] for p in params)
-    out = {"chains": len(params), "spins": spins, "steps": steps, "ms_per_step": ms,
+    out = {"chains": len(params), "spins": spins, "steps": steps, "ms_per_step": ms, "ms_per_step_plain": ms_plain,
            "attempts_per_s": attempts / (ms / 1e3), "schedule": sched,
            "rechecks": int(sum(o["rechecks"] for o in obs)),
            "attempts_total": int(sum(o["attempts"] for o in obs))}
@@ -138,7 +211,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nsw100", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the batched and mixed-precision legs")
+                    help="skip the batched, mixed-precision, annealing and colouring legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the SCO step "
@@ -169,6 +242,9 @@ def main() -> int:
     value = N * p["n_sw"] / (ms_per_step / 1e3)
     obs = sco.observables()[0]
     progress(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} attempts/s")
+    # the same steps as plain launches, for comparison (the chain moves on: later steps)
+    ms_plain = time_steps(sco, 1000 + first, args.steps, torch, graph=False)
+    progress(f"plain launches: {ms_plain:.3f} ms/step")
 
     # one traced step: block 0's phase marks inside the persistent kernel
     sco.trace(True)
@@ -210,7 +286,9 @@ def main() -> int:
         sco100.set_schedule(*[sched["blocks"], sched["tile_limit"]])
         sco100.run(0, 1)
         ms100 = time_steps(sco100, 1, 3, torch)
-        extra["n_sw_100"] = {"ms_per_step": ms100, "value": N * 100 / (ms100 / 1e3)}
+        o100 = sco100.counters()[0]  # raises if a step flagged an error
+        extra["n_sw_100"] = {"ms_per_step": ms100, "value": N * 100 / (ms100 / 1e3),
+                             "attempts": o100["attempts"], "flags": o100["flags"]}
         progress(f"n_sw=100: {ms100:.3f} ms/step")
         sco100.close()
     if not args.no_workloads:
@@ -227,6 +305,8 @@ def main() -> int:
                                                      "identical_spins": bool(same),
                                                      "speedup": r0["ms_per_step"] / r1["ms_per_step"]}
         extra["workloads"] = legs
+        extra["anneal"] = anneal_leg(torch, SCO, ChainParams)
+        extra["coloring_variants"] = coloring_leg(torch, SCO, ChainParams, p)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,7 +323,8 @@ def main() -> int:
                "kind": "oracle",
                "sample": f"{args.cpu_steps} SCO steps (switch+colour+{p['n_sw']} sweep) of the same "
                          f"L={p['L']} chain from its initial spins, single host thread, "
-                         f"{dt:.1f} s"}
+                         f"{dt:.1f} s",
+               "host": host_cpu()}
         progress(f"cpu baseline {cpu['value']:.4g} attempts/s")
 
     out = {
@@ -254,6 +335,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_plain_launches": ms_plain,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
