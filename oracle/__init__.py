@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
         ("J", ctypes.c_double), ("D", ctypes.c_double), ("T", ctypes.c_double),
         ("kappa", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("chain_id", ctypes.c_uint32),
-        ("coloring", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("coloring", ctypes.c_int32), ("model", ctypes.c_int32),
     ]
 
 
@@ -54,6 +54,7 @@ class Obs(ctypes.Structure):
         ("kw_levels", ctypes.c_int32),
         ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
         ("near_ties", ctypes.c_int64), ("delta_sco", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("m_phi", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -101,6 +102,12 @@ def lib():
         L.orc_partner.argtypes = [P, ctypes.c_int, ctypes.c_int]; L.orc_partner.restype = ctypes.c_int
         L.orc_reset_counters.argtypes = [P]; L.orc_reset_counters.restype = None
         L.orc_set_temperature.argtypes = [P, ctypes.c_double]; L.orc_set_temperature.restype = ctypes.c_int
+        L.orc_get_spins3.argtypes = [P, P]; L.orc_get_spins3.restype = None
+        L.orc_set_spins3.argtypes = [P, P]; L.orc_set_spins3.restype = None
+        L.orc_pair_energy.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_pair_energy.restype = ctypes.c_double
+        L.orc_sphere_point.argtypes = [P] + [ctypes.c_uint32] * 4 + [P]
+        L.orc_sphere_point.restype = ctypes.c_int
         for name in ("orc_color_rule2", "orc_color_whole_rule2"):
             getattr(L, name).argtypes = [P, P, ctypes.POINTER(ctypes.c_int64)]
             getattr(L, name).restype = ctypes.c_int
@@ -142,11 +149,12 @@ class ChainParams:
     seed: int = 1
     chain_id: int = 0
     coloring: int = 0  # 0 KW (2)', 1 checkerboard x KW of the bonds, 2 whole-graph BCR (2)'
+    model: int = 0     # 0 perpendicular Ising, 1 Heisenberg with the full dipolar tensor
 
     def to_c(self) -> Params:
         return Params(self.L, int(self.periodic), self.n_images, self.n_sw, self.J, self.D,
                       self.T, self.kappa, self.seed & 0xFFFFFFFF, self.chain_id & 0xFFFFFFFF,
-                      int(self.coloring), 0)
+                      int(self.coloring), int(self.model))
 
 
 class OracleChain:
@@ -198,6 +206,23 @@ class OracleChain:
     def spins(self, s: np.ndarray) -> None:
         a = np.ascontiguousarray(s, dtype=np.int8)
         lib().orc_set_spins(self._h, _ptr(a))
+
+    @property
+    def spins3(self) -> np.ndarray:
+        """Heisenberg spins, shape (N, 3)."""
+        out = np.empty((self.N, 3), np.float64)
+        lib().orc_get_spins3(self._h, _ptr(out))
+        return out
+
+    @spins3.setter
+    def spins3(self, s: np.ndarray) -> None:
+        a = np.ascontiguousarray(s, dtype=np.float64).reshape(self.N, 3)
+        lib().orc_set_spins3(self._h, _ptr(a))
+
+    def sphere_point(self, c0: int, c1: int, c2: int, tag: int):
+        out = np.empty(3, np.float64)
+        ok = lib().orc_sphere_point(self._h, c0, c1, c2, tag, _ptr(out))
+        return out if ok else None
 
     def tables(self) -> dict:
         K = self.K
@@ -278,6 +303,13 @@ class OracleChain:
         E = np.empty(max(n, 1)); M = np.empty(max(n, 1), np.int64)
         t = lib().orc_run_record(self._h, t0, n_steps, thin, _ptr(E), _ptr(M))
         return int(t), E[:n], M[:n]
+
+
+def pair_energy(si, sj, dx: int, dy: int, Jm: float) -> float:
+    """The oracle's dipolar pair energy of Eq. (6) (Jm = V^max = 2 D / r^3)."""
+    a = np.ascontiguousarray(si, dtype=np.float64)
+    b = np.ascontiguousarray(sj, dtype=np.float64)
+    return lib().orc_pair_energy(_ptr(a), _ptr(b), int(dx), int(dy), float(Jm))
 
 
 def autocorrelation_periodic(spins: np.ndarray, L: int) -> np.ndarray:

@@ -47,7 +47,10 @@ typedef struct {
   /* colouring of Fig. 1 step (2): 0 KW with rule (2)' on the union graph; 1 the
    * checkerboard product 2 c + ((x + y) mod 2), c a KW colouring of the bonds alone;
    * 2 basic colour reduction with rule (2)' on the whole union graph, no KW groups */
-  int32_t coloring, pad;
+  int32_t coloring;
+  /* 0: Ising spins perpendicular to the plane; 1: classical Heisenberg spins with the
+   * full dipolar tensor of Eq. (6) (open lattices, V^max = 2 D / r^3 per pair) */
+  int32_t model;
 } orc_params;
 
 typedef struct {
@@ -56,9 +59,10 @@ typedef struct {
   int32_t delta_union, q, colors_used, kw_levels;
   int64_t kw_rounds, accepted, attempts, near_ties;
   int32_t delta_sco, pad; /* maximum degree of the switched graph alone */
+  double m_phi;           /* Eq. (7) before the average and modulus (Heisenberg; 0 for Ising) */
 } orc_obs;
 
-enum { TAG_INIT = 1, TAG_SW = 2, TAG_TH = 3, TAG_MC = 4 };
+enum { TAG_INIT = 1, TAG_SW = 2, TAG_TH = 3, TAG_MC = 4, TAG_HP = 5, TAG_HA = 6 };
 
 /* ---------------------------------------------------------------- Philox4x32-10
  * Salmon et al. (SC'11), Sec. 3.2: ten rounds of two 32x32->64 multiplications
@@ -94,6 +98,39 @@ static void draw(const orc_params* p, uint32_t c0, uint32_t c1, uint32_t c2, uin
   orc_philox(ctr, key, out);
 }
 
+/* A point uniform on the unit sphere by Marsaglia's method (Ann. Math. Stat. 43, 645
+ * (1972)): x1, x2 uniform in (-1, 1) until q = x1^2 + x2^2 < 1, then
+ * (2 x1 sqrt(1-q), 2 x2 sqrt(1-q), 1 - 2q).  Try k uses Philox(c0, c1, c2, tag + 256 k);
+ * after 64 rejected tries there is no point (returns 0).  Only a square root is
+ * involved, so every evaluation that rounds correctly gives the same bits. */
+static int sphere_point(const orc_params* p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double out[3]) {
+  for (uint32_t k = 0; k < 64; ++k) {
+    uint32_t w[4];
+    draw(p, c0, c1, c2, tag + (k << 8), w);
+    double x1 = 2.0 * orc_u52(w[0], w[1]) - 1.0;
+    double x2 = 2.0 * orc_u52(w[2], w[3]) - 1.0;
+    double q = x1 * x1 + x2 * x2;
+    if (q < 1.0) {
+      double t = sqrt(1.0 - q);
+      out[0] = 2.0 * x1 * t;
+      out[1] = 2.0 * x2 * t;
+      out[2] = 1.0 - 2.0 * q;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+/* Dipolar pair energy of Eq. (6) for in-plane displacement (dx, dy):
+ * V = (D / r^3) [S_i . S_j - 3 (S_i . r)(S_j . r) / r^2], with D / r^3 = J_m / 2. */
+static double pair_energy(const double* si, const double* sj, int dx, int dy, double Jm) {
+  double dot = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+  double pi = si[0] * (double)dx + si[1] * (double)dy;
+  double pj = sj[0] * (double)dx + sj[1] * (double)dy;
+  double r2 = (double)dx * (double)dx + (double)dy * (double)dy;
+  return (Jm * 0.5) * (dot - 3.0 * (pi * pj) / r2);
+}
+
 /* ---------------------------------------------------------------- chain state */
 typedef struct {
   orc_params p;
@@ -103,6 +140,8 @@ typedef struct {
   int32_t *hdx, *hdy;
   double *Jm, *Cm, *theta, *delta;
   int8_t* s;
+  double* s3;   /* Heisenberg spins, (x, y, z) per site */
+  double* hden; /* Heisenberg: expm1(-2 beta J_m), J_m = V^max of the pair */
   /* switched-bond graph (both directions), rows ascending by neighbour */
   int64_t n_edges, cap;
   int32_t *sv_owner, *sv_nb, *sv_m; /* survivors in draw order */
@@ -132,7 +171,10 @@ static int cmp_disp(const void* a, const void* b) {
 static double coupling(const orc_params* p, int dx, int dy) {
   if (!p->periodic) {
     double r2 = (double)dx * (double)dx + (double)dy * (double)dy;
-    return p->D / (r2 * sqrt(r2));
+    /* Heisenberg: the bound V^max = 2 D / r^3 of the pair (the largest eigenvalue
+     * magnitude of the dipolar tensor (D / r^3)(I - 3 rhat rhat)) */
+    double Dc = p->model == 1 ? 2.0 * p->D : p->D;
+    return Dc / (r2 * sqrt(r2));
   }
   double acc = 0.0;
   int n = p->n_images, L = p->L;
@@ -183,6 +225,12 @@ static int neighbours(const orc_chain* c, int v, int nb[4]) {
 /* The temperature-dependent columns of the table at beta = 1/T. */
 static void temperature_columns(orc_chain* c) {
   const orc_params* p = &c->p;
+  if (p->model == 1) {
+    /* a candidate of the bound rate 2 beta J_m survives with probability
+     * (1 - P_ij) / pbar_m, pbar_m = 1 - exp(-2 beta J_m) = -hden_m (Eqs. 1-2) */
+    for (int m = 0; m < c->K; ++m) c->hden[m] = expm1(-c->beta * 2.0 * c->Jm[m]);
+    return;
+  }
   for (int m = 0; m < c->K; ++m) {
     double Jd = c->Jm[m];
     /* Eq. (2) with V = J s_i s_j and V^max = kappa J:
@@ -211,7 +259,7 @@ int orc_set_temperature(orc_chain* c, double T) {
 void orc_destroy(orc_chain* c) {
   if (!c) return;
   free(c->hdx); free(c->hdy); free(c->Jm); free(c->Cm); free(c->theta); free(c->delta);
-  free(c->s); free(c->sv_owner); free(c->sv_nb); free(c->sv_m);
+  free(c->s); free(c->s3); free(c->hden); free(c->sv_owner); free(c->sv_nb); free(c->sv_m);
   free(c->row_ptr); free(c->col); free(c->attr); free(c->kw_rounds_level); free(c->color);
   free(c);
 }
@@ -220,6 +268,8 @@ void orc_destroy(orc_chain* c) {
 orc_chain* orc_create(const orc_params* p, const int8_t* init_spins) {
   if (p->L < 2 || p->T <= 0.0 || !(p->kappa >= 1.0) || p->n_sw < 0 || p->n_images < 0) return NULL;
   if (p->periodic && (p->L < 4 || (p->L & 1))) return NULL;
+  if (p->model != 0 && p->model != 1) return NULL;
+  if (p->model == 1 && (p->periodic || p->kappa != 1.0)) return NULL; /* open, V^max = 2 D / r^3 */
   orc_chain* c = (orc_chain*)calloc(1, sizeof(orc_chain));
   c->p = *p;
   c->L = p->L;
@@ -259,6 +309,7 @@ orc_chain* orc_create(const orc_params* p, const int8_t* init_spins) {
   c->Cm = (double*)malloc(sizeof(double) * K);
   c->theta = (double*)malloc(sizeof(double) * K);
   c->delta = (double*)malloc(sizeof(double) * K);
+  c->hden = (double*)malloc(sizeof(double) * K);
   double acc = 0.0;
   for (int m = 0; m < K; ++m) {
     c->hdx[m] = d[2 * m];
@@ -272,7 +323,13 @@ orc_chain* orc_create(const orc_params* p, const int8_t* init_spins) {
   temperature_columns(c);
 
   c->s = (int8_t*)malloc((size_t)N);
+  c->s3 = (double*)calloc(3 * (size_t)N, sizeof(double));
   for (int v = 0; v < N; ++v) {
+    if (p->model == 1) { /* uniform on the sphere (never rejected in practice) */
+      if (!sphere_point(p, 0u, (uint32_t)v, 0u, TAG_INIT, c->s3 + 3 * (size_t)v)) c->s3[3 * (size_t)v + 2] = 1.0;
+      c->s[v] = 1;
+      continue;
+    }
     if (init_spins) { c->s[v] = init_spins[v] > 0 ? 1 : -1; continue; }
     uint32_t w[4];
     draw(p, 0u, (uint32_t)v, 0u, TAG_INIT, w);
@@ -335,7 +392,17 @@ int orc_switch(orc_chain* c, uint64_t t) {
       int m = lo;
       if (near(target, c->Cm[m]) || (m - 1 > pos && near(target, c->Cm[m - 1]))) c->near_ties++;
       int j = partner(c, i, m);
-      if (j >= 0) {
+      if (j >= 0 && c->p.model == 1) {
+        /* Heisenberg: survive with probability (1 - P_ij) / pbar_m, P_ij of Eq. (2)
+         * at the current spins */
+        uint32_t w2[4];
+        draw(&c->p, (uint32_t)t, (uint32_t)i, (uint32_t)k, TAG_TH, w2);
+        double u = orc_u52(w2[0], w2[1]);
+        double V = pair_energy(c->s3 + 3 * (size_t)i, c->s3 + 3 * (size_t)j, c->hdx[m], c->hdy[m], c->Jm[m]);
+        double ratio = expm1(c->beta * (V - c->Jm[m])) / c->hden[m];
+        if (fabs(u - ratio) < 1e-12) c->near_ties++;
+        if (u < ratio) push_survivor(c, i, j, m);
+      } else if (j >= 0) {
         int keep = (c->s[i] != c->s[j]);
         if (!keep && !c->hard) {
           uint32_t w2[4];
@@ -626,7 +693,63 @@ int orc_color_whole_rule2(orc_chain* c, int32_t* out, int64_t* rounds) {
  * s_v changes H' by s_v h_v, h_v = 2J sum_NN s_u - sum_bonds delta_m s_u, where
  * delta_m = Vbar(+1) - Vbar(-1).  With kappa == 1 a bond's parallel state has
  * infinite pseudo-energy, so a spin carrying a surviving bond never flips. */
+/* Pseudo-interaction of Eq. (3) for Heisenberg spins: Vbar = V - T log(1 - P),
+ * 1 - P = -expm1(beta (V - V^max)); +inf where 1 - P is not positive. */
+static double heis_vbar(const orc_chain* c, const double* si, const double* sj, int m) {
+  double V = pair_energy(si, sj, c->hdx[m], c->hdy[m], c->Jm[m]);
+  double g = -expm1(c->beta * (V - c->Jm[m]));
+  return g > 0.0 ? V - c->p.T * log(g) : INFINITY;
+}
+
+/* Heisenberg Metropolis on H' (Eq. 4): spin v proposes S' uniform on the sphere
+ * (sphere_point with Philox(t, v, s, TAG_HP + 256 k)) and the local energy is
+ * -J S.h + sum over its bonds of Vbar, h the sum of its lattice neighbours (+x, -x,
+ * +y, -y), the bonds in row order; dE = E(S') - E(S) is accepted when dE <= 0, else
+ * when u < exp(-beta dE), u from Philox(t, v, s, TAG_HA). */
+static void heis_sweep(orc_chain* c, uint64_t t, int n_sw) {
+  int N = c->N;
+  const int np = c->p.coloring == 1 ? 2 * c->q : c->q; /* every colour class */
+  for (int s = 0; s < n_sw; ++s)
+    for (int col = 0; col < np; ++col)
+      for (int v = 0; v < N; ++v) {
+        if (c->color[v] != col) continue;
+        c->attempts++;
+        double* S = c->s3 + 3 * (size_t)v;
+        double Sn[3];
+        if (!sphere_point(&c->p, (uint32_t)t, (uint32_t)v, (uint32_t)s, TAG_HP, Sn)) continue;
+        int nb[4], n = neighbours(c, v, nb);
+        double h[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < n; ++a)
+          for (int k = 0; k < 3; ++k) h[k] += c->s3[3 * (size_t)nb[a] + k];
+        double Eold = (-c->p.J) * (S[0] * h[0] + S[1] * h[1] + S[2] * h[2]);
+        double Enew = (-c->p.J) * (Sn[0] * h[0] + Sn[1] * h[1] + Sn[2] * h[2]);
+        for (int x = c->row_ptr[v]; x < c->row_ptr[v + 1]; ++x) {
+          const double* Sj = c->s3 + 3 * (size_t)c->col[x];
+          Eold += heis_vbar(c, S, Sj, c->attr[x]);
+          Enew += heis_vbar(c, Sn, Sj, c->attr[x]);
+        }
+        double dE = Enew - Eold;
+        int acc = 1;
+        if (!(dE <= 0.0)) {
+          uint32_t w[4];
+          draw(&c->p, (uint32_t)t, (uint32_t)v, (uint32_t)s, TAG_HA, w);
+          double u = orc_u52(w[0], w[1]);
+          double pr = exp(-c->beta * dE);
+          if (fabs(u - pr) < 1e-12) c->near_ties++;
+          acc = u < pr;
+        }
+        if (acc) {
+          S[0] = Sn[0]; S[1] = Sn[1]; S[2] = Sn[2];
+          c->accepted++;
+        }
+      }
+}
+
 int orc_sweep(orc_chain* c, uint64_t t, int n_sw) {
+  if (c->p.model == 1) {
+    heis_sweep(c, t, n_sw);
+    return 0;
+  }
   int N = c->N;
   /* every colour class of the palette: q colours, 2 q for the checkerboard product */
   const int np = c->p.coloring == 1 ? 2 * c->q : c->q;
@@ -669,9 +792,49 @@ int orc_step(orc_chain* c, uint64_t t) {
  * E = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j, the second sum taken pair by
  * pair through the owner rule (O(N K): used for small lattices; the Python layer
  * evaluates the same sum from FFT autocorrelations for large ones). */
+/* Heisenberg: E_exchange = -J sum over (+x, +y) lattice pairs of S_i . S_j (sites
+ * ascending), E_dipolar = sum over m of (sum over owners i ascending of V(S_i, S_i+d_m)),
+ * and Eq. (7) before the average: (1/N) sum_i [S_i x (r_i - r_c) / |r_i - r_c|]_z with
+ * r_c the centre of the lattice ((L-1)/2, (L-1)/2) (a site at the centre adds 0). */
+static void heis_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
+  int N = c->N, L = c->L;
+  double ex = 0.0, mphi = 0.0;
+  for (int v = 0; v < N; ++v) {
+    int x = v % L, y = v / L;
+    const double* S = c->s3 + 3 * (size_t)v;
+    if (x + 1 < L) {
+      const double* R = S + 3;
+      ex += S[0] * R[0] + S[1] * R[1] + S[2] * R[2];
+    }
+    if (y + 1 < L) {
+      const double* U = S + 3 * (size_t)L;
+      ex += S[0] * U[0] + S[1] * U[1] + S[2] * U[2];
+    }
+    double rx = (double)x - 0.5 * (double)(L - 1), ry = (double)y - 0.5 * (double)(L - 1);
+    double d = sqrt(rx * rx + ry * ry);
+    if (d > 0.0) mphi += (S[0] * ry - S[1] * rx) / d;
+  }
+  double Edip = 0.0;
+  if (with_dipolar)
+    for (int m = 0; m < c->K; ++m) {
+      double em = 0.0;
+      for (int i = 0; i < N; ++i) {
+        int j = partner(c, i, m);
+        if (j >= 0) em += pair_energy(c->s3 + 3 * (size_t)i, c->s3 + 3 * (size_t)j, c->hdx[m], c->hdy[m], c->Jm[m]);
+      }
+      Edip += em;
+    }
+  o->E_exchange = -c->p.J * ex;
+  o->E_dipolar = Edip;
+  o->E = o->E_exchange + Edip;
+  o->M = 0;
+  o->m_phi = mphi / (double)N;
+}
+
 void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
   int N = c->N;
   int64_t M = 0, ex = 0;
+  o->m_phi = 0.0;
   for (int v = 0; v < N; ++v) {
     M += c->s[v];
     int L = c->L, x = v % L, y = v / L;
@@ -684,7 +847,7 @@ void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
     }
   }
   double Edip = 0.0;
-  if (with_dipolar) {
+  if (with_dipolar && c->p.model == 0) {
     for (int m = 0; m < c->K; ++m) {
       int64_t cm = 0;
       for (int i = 0; i < N; ++i) {
@@ -707,6 +870,7 @@ void orc_observables(orc_chain* c, orc_obs* o, int with_dipolar) {
   o->E_dipolar = Edip;
   o->E = o->E_exchange + Edip;
   o->M = M;
+  if (c->p.model == 1) heis_observables(c, o, with_dipolar);
   o->n_edges = c->n_edges;
   o->delta_union = c->delta_union;
   o->q = c->q;
@@ -756,6 +920,14 @@ void orc_get_csr(const orc_chain* c, int32_t* row_ptr, int32_t* col, int32_t* at
 void orc_get_colors(const orc_chain* c, int32_t* out) { memcpy(out, c->color, (size_t)c->N * sizeof(int32_t)); }
 void orc_get_kw_rounds(const orc_chain* c, int32_t* out64) { memcpy(out64, c->kw_rounds_level, 64 * sizeof(int32_t)); }
 int orc_partner(const orc_chain* c, int i, int m) { return partner(c, i, m); }
+void orc_get_spins3(const orc_chain* c, double* out) { memcpy(out, c->s3, 3 * (size_t)c->N * sizeof(double)); }
+void orc_set_spins3(orc_chain* c, const double* in) { memcpy(c->s3, in, 3 * (size_t)c->N * sizeof(double)); }
+double orc_pair_energy(const double* si, const double* sj, int dx, int dy, double Jm) {
+  return pair_energy(si, sj, dx, dy, Jm);
+}
+int orc_sphere_point(const orc_chain* c, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double* out) {
+  return sphere_point(&c->p, c0, c1, c2, tag, out);
+}
 void orc_reset_counters(orc_chain* c) { c->accepted = c->attempts = c->near_ties = 0; }
 
 /* Per-pair survival counts over n_steps switching passes with the spins held fixed
