@@ -10,10 +10,15 @@
  *       Fig. 1 step (2)),
  *   (3) n_sw Metropolis sweeps of the switched Hamiltonian H' (Eq. 4), one
  *       colour class at a time (Fig. 1 step (3)).
- * The model is the perpendicular-Ising form of Eq. (6):
- *     H = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j,  s_i = +-1,
- * with J_ij = D / r_ij^3 on an open L x L lattice, or J_ij summed over the
- * periodic images |n_x|, |n_y| <= n_images of a periodic one.
+ * Two models of Eq. (6):
+ *   - Ising spins perpendicular to the plane (model 0):
+ *       H = -J sum_<ij> s_i s_j + sum_{i<j} J_ij s_i s_j,  s_i = +-1,
+ *     with J_ij = D / r_ij^3 on an open L x L lattice, or J_ij summed over the
+ *     periodic images |n_x|, |n_y| <= n_images of a periodic one;
+ *   - classical Heisenberg spins (model 1, open lattices, the paper's Sec. 3.1):
+ *       H = -J sum_<ij> S_i . S_j + D sum_{i<j} [S_i . S_j / r^3 - 3 (S_i . r)(S_j . r) / r^5],
+ *     switched with the pair bound V^max = 2 D / r^3 (the largest eigenvalue magnitude
+ *     of the dipolar tensor); proposals uniform on the sphere.
  *
  * Conventions shared by every call
  *   - All device memory belongs to the caller: one workspace of
@@ -71,6 +76,9 @@ typedef struct {
   uint32_t chain_id;  /* Philox key word 1 */
   int32_t precision;  /* 0: FP64 decisions; 1: FP32 accumulation + FP64 recheck (same chain) */
   int32_t edge_factor;/* directed-bond capacity per site, 0 .. 256 (0: default 4) */
+  int32_t model;      /* 0: perpendicular Ising; 1: Heisenberg (open, kappa 1, precision 0);
+                         every chain of a context has the same model */
+  int32_t pad;
 } sco_chain_params;
 
 /* Per-chain observables and counters, FP64 / exact integers. */
@@ -97,6 +105,10 @@ typedef struct {
                          (the only decisions a host evaluation may take differently) */
   int32_t delta_sco;  /* maximum degree of the switched graph alone (Table 1's Delta) */
   int32_t pad;
+  double m_phi;       /* Heisenberg: Eq. (7) before its thermal average and modulus,
+                         (1/N) sum_i [S_i x (r_i - r_c) / |r_i - r_c|]_z with r_c the centre
+                         ((L-1)/2, (L-1)/2); 0 for Ising.  (Heisenberg: M = 0, E_exchange =
+                         -J sum S_i . S_j over lattice pairs.) */
 } sco_obs;
 
 /* Statistics of one chain over one stage of an annealing schedule (sco_anneal). */
@@ -110,6 +122,8 @@ typedef struct {
   double delta_sco_mean;   /* mean of its maximum degree (Table 1's <Delta>) */
   double delta_union_mean; /* mean maximum degree of the coloured union graph */
   double acceptance;       /* accepted / attempted flips over the whole stage */
+  double m_phi;            /* Heisenberg: M_phi of Eq. (7) (before the modulus) at the end of the
+                              stage; abs_m and m2 are 0 for Heisenberg chains */
 } sco_stage;
 
 typedef struct sco_ctx sco_ctx;
@@ -158,6 +172,7 @@ int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
  *   dev_spins_out  the spins after steps first_step .. first_step + n_steps - 1, same
  *                  layout (may equal dev_spins_in)
  *   host_obs       NULL, or n_chains observables after the steps
+ * Ising chains only (SCO_EINVAL for Heisenberg parameters).
  * Returns SCO_OK or an error code as sco_init / sco_run; synchronises `stream`.  Every
  * call on one GPU uses that GPU's one array and re-initialises it: calls that overlap
  * on one GPU (other host threads, other streams) race and must be serialised by the
@@ -203,9 +218,15 @@ int sco_observables(sco_ctx* ctx, sco_obs* host_out);
  * graph statistics and counters only, in O(N).  Synchronises. */
 int sco_counters(sco_ctx* ctx, sco_obs* host_out);
 
-/* Checkpoint / resume: spins of one chain (N int8 values) to / from host memory. */
+/* Checkpoint / resume: spins of one chain (N int8 values) to / from host memory
+ * (Ising contexts; SCO_EINVAL for Heisenberg). */
 int sco_get_spins(sco_ctx* ctx, int chain, int8_t* host_out);
 int sco_set_spins(sco_ctx* ctx, int chain, const int8_t* host_in);
+
+/* The same for Heisenberg spins: 3 N doubles, (x, y, z) per site, row-major sites
+ * (SCO_EINVAL for Ising contexts or a non-finite component). */
+int sco_get_spins3(sco_ctx* ctx, int chain, double* host_out);
+int sco_set_spins3(sco_ctx* ctx, int chain, const double* host_in);
 
 /* The last switched graph of one chain, in site numbers local to the chain:
  * row_ptr[N+1], col[n_dir], attr[n_dir] (half-displacement index of the bond),

@@ -367,6 +367,8 @@ def anneal(chain: OracleChain, temps, equil_steps: int, meas_steps: int, first_s
         o = chain.observables()
         ns = float(meas_steps)
         att = o["attempts"] - acc0["attempts"]
+        if chain.params.model == 1:  # the magnetisation is an Ising sum
+            s_abs = s_m2 = 0
         out.append(dict(
             T=float(T), E=o["E"], M=int(o["M"]), samples=meas_steps,
             abs_m=(float(s_abs) / ns / N) if meas_steps else 0.0,
@@ -375,5 +377,6 @@ def anneal(chain: OracleChain, temps, equil_steps: int, meas_steps: int, first_s
             delta_sco_mean=(float(s_ds) / ns) if meas_steps else 0.0,
             delta_union_mean=(float(s_du) / ns) if meas_steps else 0.0,
             acceptance=(float(o["accepted"] - acc0["accepted"]) / att) if att else 0.0,
-            spins=chain.spins))
+            m_phi=o["m_phi"],
+            spins=chain.spins3 if chain.params.model == 1 else chain.spins))
     return out

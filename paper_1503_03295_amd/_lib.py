@@ -15,8 +15,9 @@ EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
     "sco_observables", "sco_get_spins", "sco_set_spins", "sco_get_graph", "sco_get_tables",
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
-    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags", "sco_counters", "sco_run_noalloc", "sco_run_graph",
-    "sco_set_temperature", "sco_anneal", "sco_set_coloring",
+    "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags",
+    "sco_counters", "sco_run_noalloc", "sco_run_graph", "sco_set_temperature", "sco_anneal",
+    "sco_set_coloring", "sco_get_spins3", "sco_set_spins3",
 ]
 
 
@@ -28,6 +29,7 @@ class ChainParamsC(ctypes.Structure):
         ("kappa", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("chain_id", ctypes.c_uint32),
         ("precision", ctypes.c_int32), ("edge_factor", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -39,7 +41,7 @@ class ObsC(ctypes.Structure):
         ("kw_levels", ctypes.c_int32),
         ("kw_rounds", ctypes.c_int64), ("accepted", ctypes.c_int64), ("attempts", ctypes.c_int64),
         ("rechecks", ctypes.c_int64), ("flags", ctypes.c_int64), ("near_ties", ctypes.c_int64),
-        ("delta_sco", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("delta_sco", ctypes.c_int32), ("pad", ctypes.c_int32), ("m_phi", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -55,7 +57,7 @@ class StageC(ctypes.Structure):
         ("T", ctypes.c_double), ("E", ctypes.c_double), ("M", ctypes.c_int64), ("samples", ctypes.c_int64),
         ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("k_mean", ctypes.c_double),
         ("delta_sco_mean", ctypes.c_double), ("delta_union_mean", ctypes.c_double),
-        ("acceptance", ctypes.c_double),
+        ("acceptance", ctypes.c_double), ("m_phi", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -95,6 +97,8 @@ def lib():
         "sco_run_graph": ([P, u64, i32], i32),
         "sco_set_temperature": ([P, i32, ctypes.c_double], i32),
         "sco_set_coloring": ([P, i32], i32),
+        "sco_get_spins3": ([P, i32, P], i32),
+        "sco_set_spins3": ([P, i32, P], i32),
         "sco_anneal": ([P, ctypes.POINTER(ctypes.c_double), i32, i32, i32, u64, ctypes.POINTER(StageC)], i32),
         "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),
         "sco_counters": ([P, ctypes.POINTER(ObsC)], i32),

@@ -31,11 +31,12 @@ class ChainParams:
     chain_id: int = 0
     precision: int = 0  # 0 FP64, 1 FP32 accumulation + FP64 recheck
     edge_factor: int = 0
+    model: int = 0      # 0 perpendicular Ising, 1 Heisenberg with the full dipolar tensor (open)
 
     def to_c(self) -> ChainParamsC:
         return ChainParamsC(self.L, int(self.periodic), self.n_images, self.n_sw, self.J, self.D,
                             self.T, self.kappa, self.seed & 0xFFFFFFFF, self.chain_id & 0xFFFFFFFF,
-                            self.precision, self.edge_factor)
+                            self.precision, self.edge_factor, self.model, 0)
 
 
 def workspace_size(params: list[ChainParams]) -> int:
@@ -160,6 +161,18 @@ class SCO:
         out = np.empty(p.L * p.L, np.int8)
         check(lib().sco_get_spins(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)), "sco_get_spins", self._h)
         return out
+
+    def spins3(self, chain: int = 0) -> np.ndarray:
+        """Heisenberg spins of a chain, shape (N, 3)."""
+        p = self.params[chain]
+        out = np.empty((p.L * p.L, 3), np.float64)
+        check(lib().sco_get_spins3(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)), "sco_get_spins3", self._h)
+        return out
+
+    def set_spins3(self, chain: int, spins: np.ndarray) -> None:
+        p = self.params[chain]
+        a = np.ascontiguousarray(spins, dtype=np.float64).reshape(p.L * p.L, 3)
+        check(lib().sco_set_spins3(self._h, chain, a.ctypes.data_as(ctypes.c_void_p)), "sco_set_spins3", self._h)
 
     def set_spins(self, chain: int, spins: np.ndarray) -> None:
         a = np.ascontiguousarray(spins, dtype=np.int8)

@@ -34,8 +34,15 @@ bool valid(const sco_chain_params& p) {
   if (p.n_sw < 0 || p.n_images < 0 || p.n_images > 64) return false;
   if (p.precision != 0 && p.precision != 1) return false;
   if (p.edge_factor < 0 || p.edge_factor > 256) return false;
+  if (p.model != SCO_MODEL_ISING && p.model != SCO_MODEL_HEIS) return false;
+  // Heisenberg spins: open lattices (Sec. 3.1), V^max = 2 D / r^3, FP64 decisions
+  if (p.model == SCO_MODEL_HEIS && (p.periodic || p.kappa != 1.0 || p.precision != 0)) return false;
   return true;
 }
+
+// the displacement table's coupling constant: J_m = D / r^3 for Ising spins, the bound
+// V^max = 2 D / r^3 of the dipolar tensor for Heisenberg spins
+double table_d(const sco_chain_params& p) { return p.model == SCO_MODEL_HEIS ? 2.0 * p.D : p.D; }
 
 using TableKey = std::tuple<int, int, int, double>;  // L, periodic, n_images, D
 
@@ -54,7 +61,7 @@ struct Layout {
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
-  size_t off_acc = 0;
+  size_t off_acc = 0, off_spin3 = 0, off_hpart = 0, off_hres = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -72,7 +79,8 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_st = take(sizeof(ChainState) * n);
   int64_t G = 0, edges = 0;
   for (int c = 0; c < n; ++c) {
-    const TableKey key{p[c].L, p[c].periodic ? 1 : 0, p[c].periodic ? p[c].n_images : 0, p[c].D};
+    if (p[c].model != p[0].model) return SCO_EINVAL;  // one spin model per context
+    const TableKey key{p[c].L, p[c].periodic ? 1 : 0, p[c].periodic ? p[c].n_images : 0, table_d(p[c])};
     auto it = lay.table_index.find(key);
     int t;
     if (it == lay.table_index.end()) {
@@ -108,11 +116,14 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   for (int c = 0; c < n; ++c) {
     const int64_t K = lay.table_K[lay.chain_table[c]];
     const bool hard = p[c].kappa == 1.0;
-    lay.off_theta.push_back(hard ? 0 : take(sizeof(double) * K));
+    const bool heis = p[c].model == SCO_MODEL_HEIS;
+    // theta (Ising kappa > 1) or the Heisenberg denominators expm1(-2 beta J_m)
+    lay.off_theta.push_back(hard && !heis ? 0 : take(sizeof(double) * K));
     lay.off_delta.push_back(hard ? 0 : take(sizeof(double) * K));
     lay.off_delta32.push_back(hard ? 0 : take(sizeof(float) * K));
   }
   lay.off_spin = take(G);
+  lay.off_spin3 = p[0].model == SCO_MODEL_HEIS ? take(sizeof(double) * 3 * G) : 0;
   lay.off_deg = take(sizeof(int32_t) * G);
   lay.off_row = take(sizeof(int32_t) * (G + 1));
   lay.off_fill = take(sizeof(int32_t) * G);
@@ -140,6 +151,10 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_dpart = take(sizeof(double) * (lay.maxK / 4096 + 2));
   lay.off_dres = take(sizeof(double) * n);
   lay.off_acc = take(sizeof(AnnealAcc) * n);
+  int64_t maxN = 0;
+  for (int c = 0; c < n; ++c) maxN = std::max<int64_t>(maxN, static_cast<int64_t>(p[c].L) * p[c].L);
+  lay.off_hpart = take(sizeof(double) * 2 * (maxN / 256 + 2));
+  lay.off_hres = take(sizeof(double) * 2);
   lay.bytes = off;
   return SCO_OK;
 }
@@ -178,6 +193,7 @@ void build_halfset(int L, int periodic, std::vector<uint32_t>& hd) {
 struct sco_ctx {
   hipStream_t stream = nullptr;
   int n = 0;
+  int model = SCO_MODEL_ISING;
   std::vector<sco_chain_params> params;
   Layout lay;
   char* ws = nullptr;
@@ -269,7 +285,7 @@ int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
   }
   c->args.nsw_override = nsw_override;
   c->args.nsw_max = nsw_override >= 0 ? nsw_override : c->nsw_max;
-  HIP_TRY(sco_dev::step(c->stream, c->args, phases, c->blocks));
+  HIP_TRY(sco_dev::step(c->stream, c->args, phases, c->blocks, c->model));
   return SCO_OK;
 }
 
@@ -326,9 +342,21 @@ int temperature_tables(sco_ctx* c, int ci, double T) {
     const double dE = (2.0 * p.J) * static_cast<double>(k);
     d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
   }
-  if (d.hard) return SCO_OK;
+  d.T = T;
   const int t = L.chain_table[ci];
   const int64_t K = L.table_K[t];
+  if (d.model == SCO_MODEL_HEIS) {
+    // a candidate of the bound rate 2 beta J_m survives with probability
+    // (1 - P_ij) / pbar_m, pbar_m = -expm1(-2 beta J_m) (Eqs. 1-2)
+    std::vector<double> hd(K);
+    const std::vector<double>& Jt = c->J[t];
+    for (int64_t m = 0; m < K; ++m) hd[m] = std::expm1(-beta * 2.0 * Jt[m]);
+    HIP_TRY(hipMemcpyAsync(const_cast<double*>(d.hden), hd.data(), sizeof(double) * K, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCO_OK;
+  }
+  if (d.hard) return SCO_OK;
   std::vector<double>& th = c->theta[ci];
   std::vector<double>& de = c->delta[ci];
   std::vector<float> de32(K);
@@ -387,6 +415,11 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   }
   c->stream = static_cast<hipStream_t>(stream);
   c->n = n_chains;
+  c->model = params[0].model;
+  if (c->model == SCO_MODEL_HEIS && dev_init_spins) {  // Heisenberg chains start from Philox
+    delete c;
+    return SCO_EINVAL;
+  }
   c->params.assign(params, params + n_chains);
   c->ws = static_cast<char*>(dev_workspace);
   const Layout& L = c->lay;
@@ -416,7 +449,7 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   for (size_t t = 0; t < nt; ++t) {
     const int Lt = std::get<0>(L.tables[t]), per = std::get<1>(L.tables[t]);
     const int nim = std::get<2>(L.tables[t]);
-    const double D = std::get<3>(L.tables[t]);
+    const double D = std::get<3>(L.tables[t]);  // table_d of the chains
     build_halfset(Lt, per, c->hd[t]);
     const int64_t K = static_cast<int64_t>(c->hd[t].size());
     if (K != L.table_K[t]) return fail(SCO_EINTERNAL);
@@ -483,10 +516,13 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
     d.twoJ32_exact = static_cast<double>(d.twoJ32) == d.twoJ ? 1 : 0;
     d.seed = p.seed;
     d.chain_id = p.chain_id;
-    d.hard = hard ? 1 : 0;
+    d.model = p.model;
+    d.hard = hard && p.model == SCO_MODEL_ISING ? 1 : 0;
     d.precision = p.precision;
     d.n_sw = p.n_sw;
-    if (!hard) {
+    if (p.model == SCO_MODEL_HEIS) {
+      d.hden = at<double>(c, L.off_theta[ci]);
+    } else if (!hard) {
       d.theta = at<double>(c, L.off_theta[ci]);
       d.delta = at<double>(c, L.off_delta[ci]);
       d.delta32 = at<float>(c, L.off_delta32[ci]);
@@ -507,8 +543,10 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
       hipMemcpyAsync(at<int64_t>(c, L.off_srcbase), src_base.data(), sizeof(int64_t) * n_chains,
                      hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return fail(SCO_EHIP);
+  double* spin3 = c->model == SCO_MODEL_HEIS ? at<double>(c, L.off_spin3) : nullptr;
   if (sco_dev::init_spins(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
-                          at<int64_t>(c, L.off_srcbase), dev_init_spins, at<int8_t>(c, L.off_spin), L.G) != hipSuccess)
+                          at<int64_t>(c, L.off_srcbase), dev_init_spins, at<int8_t>(c, L.off_spin), spin3,
+                          L.G) != hipSuccess)
     return fail(SCO_EHIP);
   // an empty graph until the first switching (row offsets of zero length)
   if (hipMemsetAsync(at<int32_t>(c, L.off_row), 0, sizeof(int32_t) * (L.G + 1), c->stream) != hipSuccess ||
@@ -522,6 +560,7 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   a.sync = at<SyncWords>(c, L.off_sync);
   a.chunk_chain = at<int32_t>(c, L.off_chunk);
   a.spin = at<int8_t>(c, L.off_spin);
+  a.spin3 = spin3;
   a.deg = at<int32_t>(c, L.off_deg);
   a.row_ptr = at<int32_t>(c, L.off_row);
   a.fill = at<int32_t>(c, L.off_fill);
@@ -622,6 +661,7 @@ int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
 int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* dev_spins_in,
                     int8_t* dev_spins_out, uint64_t first_step, int n_steps, sco_obs* host_obs, void* stream) {
   if (!params || n_chains <= 0 || n_chains > SCO_MAXCHAINS || !dev_spins_out || n_steps < 0) return SCO_EINVAL;
+  if (params[0].model != SCO_MODEL_ISING) return SCO_EINVAL;  // int8 spins in and out
   size_t need = 0;
   int rc = sco_workspace_size(params, n_chains, &need);
   if (rc) return rc;
@@ -667,7 +707,7 @@ int graph_build(sco_ctx* c, int n) {
   for (int s = 0; s < n; ++s) {
     void* kargs[] = {&c->graph_args[s]};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(sco_dev::step_kernel_full());
+    kp.func = const_cast<void*>(sco_dev::step_kernel_full(c->model));
     kp.gridDim = dim3(c->blocks);
     kp.blockDim = dim3(SCO_CHUNK);
     kp.sharedMemBytes = 0;
@@ -716,7 +756,7 @@ int sco_run_graph(sco_ctx* c, uint64_t first_step, int n_steps) {
     a.step = static_cast<uint32_t>(first_step + static_cast<uint64_t>(s));
     void* kargs[] = {&a};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(sco_dev::step_kernel_full());
+    kp.func = const_cast<void*>(sco_dev::step_kernel_full(c->model));
     kp.gridDim = dim3(c->blocks);
     kp.blockDim = dim3(SCO_CHUNK);
     kp.kernelParams = kargs;
@@ -786,9 +826,11 @@ int sco_anneal(sco_ctx* c, const double* temps, int n_stages, int equil_steps, i
       o.T = c->params[ci].T;
       o.E = obs[ci].E;
       o.M = obs[ci].M;
+      o.m_phi = obs[ci].m_phi;
       o.samples = static_cast<int64_t>(h[ci].samples);
-      o.abs_m = ns > 0 ? static_cast<double>(h[ci].abs_m) / ns / N : 0.0;
-      o.m2 = ns > 0 ? static_cast<double>(h[ci].m2) / ns / (N * N) : 0.0;
+      const bool ising = c->model == SCO_MODEL_ISING;  // the magnetisation is an Ising sum
+      o.abs_m = ising && ns > 0 ? static_cast<double>(h[ci].abs_m) / ns / N : 0.0;
+      o.m2 = ising && ns > 0 ? static_cast<double>(h[ci].m2) / ns / (N * N) : 0.0;
       o.k_mean = ns > 0 ? static_cast<double>(h[ci].bonds) / ns / N : 0.0;
       o.delta_sco_mean = ns > 0 ? static_cast<double>(h[ci].delta_sco) / ns : 0.0;
       o.delta_union_mean = ns > 0 ? static_cast<double>(h[ci].delta_union) / ns : 0.0;
@@ -943,8 +985,19 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   HIP_TRY(hipMemsetAsync(d_used, 0, sizeof(uint32_t) * SCO_QWORDS * c->n, c->stream));
   HIP_TRY(sco_dev::obs_basic(c->stream, at<ChainDesc>(c, L.off_cd), at<int32_t>(c, L.off_chunk),
                              at<int8_t>(c, L.off_spin), at<uint16_t>(c, L.off_color), d_obs, d_used, L.G));
-  for (int ci = 0; ci < c->n && dipolar; ++ci) {
+  const bool heis = c->model == SCO_MODEL_HEIS;
+  std::vector<double> hres(2 * c->n, 0.0);  // Heisenberg: exchange sum, M_phi sum
+  for (int ci = 0; ci < c->n && (dipolar || heis); ++ci) {
     const ChainDesc& d = c->cd[ci];
+    if (heis) {
+      HIP_TRY(sco_dev::obs_heis(c->stream, at<ChainDesc>(c, L.off_cd), ci, d, at<double>(c, L.off_spin3),
+                                at<double>(c, L.off_prod), at<double>(c, L.off_dpart), at<double>(c, L.off_dres) + ci,
+                                at<double>(c, L.off_hpart), at<double>(c, L.off_hres)));
+      HIP_TRY(hipMemcpyAsync(&hres[2 * ci], at<double>(c, L.off_hres), 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      continue;
+    }
     HIP_TRY(sco_dev::obs_dipolar(c->stream, d.hd, d.J, d.K, d.L, d.periodic, at<int8_t>(c, L.off_spin), d.vbase,
                                  at<uint32_t>(c, L.off_bits), at<double>(c, L.off_prod), at<double>(c, L.off_dpart),
                                  at<double>(c, L.off_dres) + ci));
@@ -957,7 +1010,7 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(sums.data(), d_obs, sizeof(unsigned long long) * 2 * c->n, hipMemcpyDeviceToHost, c->stream));
-  if (dipolar)
+  if (dipolar || heis)
     HIP_TRY(hipMemcpyAsync(edip.data(), at<double>(c, L.off_dres), sizeof(double) * c->n, hipMemcpyDeviceToHost,
                            c->stream));
   else
@@ -969,7 +1022,7 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
     const ChainState& s = st[ci];
     o.M = static_cast<long long>(sums[2 * ci]);
     // the magnetisation the sweeps keep must equal the sum of the spins
-    if (s.mag != o.M) bad_mag = 1;
+    if (!heis && s.mag != o.M) bad_mag = 1;
     o.E_exchange = -c->params[ci].J * static_cast<double>(static_cast<long long>(sums[2 * ci + 1]));
     o.E_dipolar = edip[ci];
     o.E = o.E_exchange + o.E_dipolar;
@@ -989,6 +1042,14 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
     o.flags = c->flags_seen;
     o.near_ties = static_cast<int64_t>(s.near_ties);
     o.delta_sco = s.delta_sco;
+    o.m_phi = 0.0;
+    if (heis) {  // Eq. (6) with Heisenberg spins and Eq. (7) before its average
+      o.M = 0;
+      o.E_exchange = -c->params[ci].J * hres[2 * ci];
+      o.E_dipolar = dipolar ? edip[ci] : std::nan("");
+      o.E = o.E_exchange + o.E_dipolar;
+      o.m_phi = hres[2 * ci + 1] / static_cast<double>(c->cd[ci].N);
+    }
   }
   if (fr == SCO_OK && bad_mag) return SCO_EINTERNAL;
   return fr;
@@ -999,8 +1060,28 @@ int sco_observables(sco_ctx* c, sco_obs* out) { return observables_impl(c, out, 
 
 int sco_counters(sco_ctx* c, sco_obs* out) { return observables_impl(c, out, false); }
 
+int sco_get_spins3(sco_ctx* c, int chain, double* host_out) {
+  if (!c || chain < 0 || chain >= c->n || !host_out || c->model != SCO_MODEL_HEIS) return SCO_EINVAL;
+  const ChainDesc& d = c->cd[chain];
+  HIP_TRY(hipMemcpyAsync(host_out, at<double>(c, c->lay.off_spin3) + 3 * d.vbase, sizeof(double) * 3 * d.N,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+int sco_set_spins3(sco_ctx* c, int chain, const double* host_in) {
+  if (!c || chain < 0 || chain >= c->n || !host_in || c->model != SCO_MODEL_HEIS) return SCO_EINVAL;
+  const ChainDesc& d = c->cd[chain];
+  for (int64_t i = 0; i < 3 * static_cast<int64_t>(d.N); ++i)
+    if (!std::isfinite(host_in[i])) return SCO_EINVAL;
+  HIP_TRY(hipMemcpyAsync(at<double>(c, c->lay.off_spin3) + 3 * d.vbase, host_in, sizeof(double) * 3 * d.N,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
 int sco_get_spins(sco_ctx* c, int chain, int8_t* host_out) {
-  if (!c || chain < 0 || chain >= c->n || !host_out) return SCO_EINVAL;
+  if (!c || chain < 0 || chain >= c->n || !host_out || c->model != SCO_MODEL_ISING) return SCO_EINVAL;
   const ChainDesc& d = c->cd[chain];
   HIP_TRY(hipMemcpyAsync(host_out, at<int8_t>(c, c->lay.off_spin) + d.vbase, d.N, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1008,7 +1089,7 @@ int sco_get_spins(sco_ctx* c, int chain, int8_t* host_out) {
 }
 
 int sco_set_spins(sco_ctx* c, int chain, const int8_t* host_in) {
-  if (!c || chain < 0 || chain >= c->n || !host_in) return SCO_EINVAL;
+  if (!c || chain < 0 || chain >= c->n || !host_in || c->model != SCO_MODEL_ISING) return SCO_EINVAL;
   const ChainDesc& d = c->cd[chain];
   std::vector<int8_t> s(d.N);
   for (int v = 0; v < d.N; ++v) s[v] = host_in[v] > 0 ? 1 : -1;

@@ -21,7 +21,11 @@
 #define SCO_BAR_GROUPS 32       // first-level arrival groups of the grid barrier
 #define SCO_NOALLOC_BYTES (64u << 20)  // static scratch of the entry point that allocates nothing
 
-enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4 };
+enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4, SCO_TAG_HP = 5, SCO_TAG_HA = 6 };
+
+// spin model of a context: perpendicular Ising spins, or classical Heisenberg spins with
+// the full dipolar tensor (open lattices)
+enum { SCO_MODEL_ISING = 0, SCO_MODEL_HEIS = 1 };
 
 enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4, SCO_FLAG_STATE = 8 };
 
@@ -47,6 +51,9 @@ struct ChainDesc {
   float inv_rate32, neg_beta32, twoJ32;  // FP32 copies (precision 1)
   int32_t twoJ32_exact;                   // 2J is exact in FP32: bond-free fields are exact
   int32_t fp32_gap;                       // precision 1 may decide switching gaps in FP32
+  int32_t model;                          // SCO_MODEL_*
+  double T;                               // temperature (Heisenberg pseudo-interactions)
+  const double* hden;                     // Heisenberg: expm1(-2 beta J_m) per m (J_m = V^max)
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
 };
@@ -89,6 +96,7 @@ struct StepArgs {
   SyncWords* sync;
   const int32_t* chunk_chain;
   int8_t* spin;
+  double* spin3;          // [3 G] Heisenberg spins (x, y, z per site), nullptr for Ising
   int32_t* deg;           // [G] degrees (cleared by the switching phase)
   int32_t* row_ptr;       // [G + 1]
   int32_t* fill;          // [G] scatter cursors: cleared, then set to each owner's survivor count
@@ -122,11 +130,15 @@ namespace sco_dev {
 hipError_t table_j(hipStream_t s, const uint32_t* hd, int K, int L, int periodic, int n_images,
                    double D, double* J);
 hipError_t init_spins(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
-                      const int64_t* src_base, const int8_t* src, int8_t* spin, int64_t G);
+                      const int64_t* src_base, const int8_t* src, int8_t* spin, double* spin3, int64_t G);
 int step_max_blocks();
-hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks);
-// The full step kernel (k_step<7>), for graph kernel nodes.
-const void* step_kernel_full();
+hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks, int model);
+// The full step kernel of a model, for graph kernel nodes.
+const void* step_kernel_full(int model);
+// Heisenberg observables: prod[m] = sum over owners of the pair energy of displacement
+// m; part2[b] = per-block (exchange sum, M_phi sum); out2 = their totals
+hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& hd, const double* spin3,
+                    double* prod, double* part, double* out, double* part2, double* out2);
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
                      const int8_t* spin, const uint16_t* color, unsigned long long* out,
                      unsigned* used, int64_t G);

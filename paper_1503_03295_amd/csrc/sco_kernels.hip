@@ -99,6 +99,39 @@ __device__ __forceinline__ double unit52(uint32_t lo, uint32_t hi) {
   return (static_cast<double>(w >> 12) + 0.5) * 0x1p-52;
 }
 
+// A point uniform on the unit sphere by Marsaglia's method (Ann. Math. Stat. 43, 645
+// (1972)): x1, x2 uniform in (-1, 1) until q = x1^2 + x2^2 < 1, then
+// (2 x1 sqrt(1-q), 2 x2 sqrt(1-q), 1 - 2q).  Try k draws Philox(c0, c1, c2, tag + 256 k);
+// false after 64 rejected tries.  Only a correctly rounded square root is involved.
+__device__ __forceinline__ bool sphere_point(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, uint32_t k0,
+                                             uint32_t k1, double& ox, double& oy, double& oz) {
+  for (uint32_t k = 0; k < 64; ++k) {
+    const W4 w = philox10(c0, c1, c2, tag + (k << 8), k0, k1);
+    const double x1 = 2.0 * unit52(w.x, w.y) - 1.0;
+    const double x2 = 2.0 * unit52(w.z, w.w) - 1.0;
+    const double q = x1 * x1 + x2 * x2;
+    if (q < 1.0) {
+      const double t = sqrt(1.0 - q);
+      ox = 2.0 * x1 * t;
+      oy = 2.0 * x2 * t;
+      oz = 1.0 - 2.0 * q;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Dipolar pair energy of Eq. (6) for in-plane displacement (dx, dy):
+// (D / r^3) [S_i . S_j - 3 (S_i . r)(S_j . r) / r^2], D / r^3 = J_m / 2 (J_m = V^max).
+__device__ __forceinline__ double heis_pair(double ax, double ay, double az, double bx, double by, double bz, int dx,
+                                            int dy, double Jm) {
+  const double dot = ax * bx + ay * by + az * bz;
+  const double pi = ax * static_cast<double>(dx) + ay * static_cast<double>(dy);
+  const double pj = bx * static_cast<double>(dx) + by * static_cast<double>(dy);
+  const double r2 = static_cast<double>(dx) * static_cast<double>(dx) + static_cast<double>(dy) * static_cast<double>(dy);
+  return (Jm * 0.5) * (dot - 3.0 * (pi * pj) / r2);
+}
+
 // ------------------------------------------------------------------ helpers
 // |a - b| <= 1e-12 |b|: a decision this close may differ from a host evaluation whose
 // exp / log differ in the last bit; such decisions are counted (near ties).
@@ -511,12 +544,24 @@ extern "C" __global__ void k_table_j(const uint32_t* __restrict__ hd, int K, int
 extern "C" __global__ void __launch_bounds__(kBlock)
     k_init_spins(const ChainDesc* __restrict__ cd, const int32_t* __restrict__ chunk_chain,
                  const int64_t* __restrict__ src_base, const int8_t* __restrict__ src,
-                 int8_t* __restrict__ spin, int64_t G) {
+                 int8_t* __restrict__ spin, double* __restrict__ spin3, int64_t G) {
   const int64_t g = gtid();
   if (g >= G) return;
   const int c = chunk_chain[g >> SCO_CHUNK_SHIFT];
   const ChainDesc& d = cd[c];
   const int v = static_cast<int>(g - d.vbase);
+  if (d.model == SCO_MODEL_HEIS) {  // uniform on the sphere, Philox(0, v, 0, INIT + 256 k)
+    double x = 0.0, y = 0.0, z = 1.0;
+    if (v < d.N && !sphere_point(0u, static_cast<uint32_t>(v), 0u, SCO_TAG_INIT, d.seed, d.chain_id, x, y, z)) {
+      x = y = 0.0;
+      z = 1.0;
+    }
+    spin3[3 * g] = x;
+    spin3[3 * g + 1] = y;
+    spin3[3 * g + 2] = z;
+    spin[g] = 1;
+    return;
+  }
   if (v >= d.N) {
     spin[g] = 1;
     return;
@@ -539,6 +584,7 @@ struct Owner {
   double Cpos;     // C at pos
   uint32_t slo, shi;  // second half of the last Philox output: the next (odd) draw
   int si;          // the owner's spin
+  double sx, sy, sz;  // the owner's Heisenberg spin
   int ns;          // survivors of the owner stored so far
   bool live;
 };
@@ -550,7 +596,7 @@ struct Owner {
 // the range belongs to chain c_uni.  Dealing owners from one pool keeps the lanes of
 // a wave (and the waves of a block) busy until the block's sites run out, instead of
 // each lane working through a fixed share whose draw count varies.
-template <class Desc>
+template <bool Heis, class Desc>
 __device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, bool need, bool& pool,
                                            uint32_t* s_next, int ch0, int ch1, int c_uni) {
   const uint32_t lane = lane_id();
@@ -583,7 +629,13 @@ __device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_o
           o.pos = -1;
           o.k = 0;
           o.Cpos = 0.0;
-          o.si = a.spin[g];
+          if constexpr (Heis) {
+            o.sx = a.spin3[3 * g];
+            o.sy = a.spin3[3 * g + 1];
+            o.sz = a.spin3[3 * g + 2];
+          } else {
+            o.si = a.spin[g];
+          }
           o.ns = 0;
           o.live = true;
           want = false;
@@ -655,7 +707,7 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTabl
 template <class Desc>
 __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& desc_of, const SwitchTables& tb,
                                                 uint32_t step, Owner& o, int& j, int& m, uint32_t& kc,
-                                                Tally& tally) {
+                                                Tally& tally, int& ddx, int& ddy) {
   const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -708,6 +760,8 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
   const uint32_t p = tb.hd_at(d, m);
   const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
   j = partner_of(o.x, o.y, dx, dy, d.L, d.periodic);
+  ddx = dx;
+  ddy = dy;
   kc = o.k;
   o.pos = m;
   o.Cpos = tb.c_at(d, m);
@@ -717,6 +771,23 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
 
 // Whether candidate (j, m, kc) of owner o survives, given the partner's spin sj:
 // antiparallel spins always, parallel ones (kappa > 1) with probability theta_m.
+// Heisenberg: the candidate survives with probability (1 - P_ij) / pbar_m =
+// expm1(beta (V_ij - V^max)) / expm1(-2 beta J_m) at the current spins (Eqs. 1-2).
+template <class Desc>
+__device__ __forceinline__ bool owner_survives_heis(const StepArgs& a, const Desc& desc_of, uint32_t step,
+                                                    const Owner& o, int j, int m, uint32_t kc, int dx, int dy,
+                                                    double bx, double by, double bz, Tally& tally) {
+  if (j < 0) return false;
+  const ChainDesc& d = desc_of(o.c);
+  const W4 t = philox10(step, static_cast<uint32_t>(o.v), kc, SCO_TAG_TH, d.seed, d.chain_id);
+  const double u = unit52(t.x, t.y);
+  const double Jm = ld_global(&d.J[m]);
+  const double V = heis_pair(o.sx, o.sy, o.sz, bx, by, bz, dx, dy, Jm);
+  const double ratio = expm1(d.beta * (V - Jm)) / ld_global(&d.hden[m]);
+  if (fabs(u - ratio) < 1e-12) tally.tie(a, o.c);
+  return u < ratio;
+}
+
 template <class Desc>
 __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t step, const Owner& o, int j, int m,
                                                uint32_t kc, int sj) {
@@ -741,6 +812,7 @@ __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t ste
 // range in flight and takes the next from the block's pool as soon as one ends, so a
 // wave is held neither by its slowest owner nor by its busiest lane.  Survivors go to the block's region (one LDS atomic per wave
 // and append); its count is written to the entry of the range's first chunk.
+template <bool Heis>
 __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, int32_t* lds_raw) {
   __shared__ uint32_t s_count, s_next;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
@@ -782,7 +854,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     for (int u = 0; u < kOwners; ++u) {
       O[u].ns = 0;
       O[u].live = false;
-      owner_take(a, desc_of, O[u], pool, pool, &s_next, ch0, ch1, c_uni);
+      owner_take<Heis>(a, desc_of, O[u], pool, pool, &s_next, ch0, ch1, c_uni);
     }
     auto any_live = [&]() {
       bool l = false;
@@ -792,7 +864,8 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     };
     while (__ballot(any_live()) != 0) {
       // every owner's candidate first, then all partner spins in flight together
-      int jc[kOwners], mc[kOwners], sc[kOwners];
+      int jc[kOwners], mc[kOwners], sc[kOwners], xc[kOwners], yc[kOwners];
+      double bx[kOwners], by[kOwners], bz[kOwners];
       uint32_t kc[kOwners];
       bool cc[kOwners];
 #pragma unroll
@@ -800,14 +873,31 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         jc[u] = -1;
         mc[u] = 0;
         kc[u] = 0;
-        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally);
+        xc[u] = yc[u] = 0;
+        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u]);
       }
 #pragma unroll
-      for (int u = 0; u < kOwners; ++u)
-        sc[u] = cc[u] && jc[u] >= 0 ? a.spin[desc_of(O[u].c).vbase + jc[u]] : 0;
+      for (int u = 0; u < kOwners; ++u) {
+        if constexpr (Heis) {
+          bx[u] = by[u] = bz[u] = 0.0;
+          if (cc[u] && jc[u] >= 0) {
+            const double* B = a.spin3 + 3 * (desc_of(O[u].c).vbase + jc[u]);
+            bx[u] = B[0];
+            by[u] = B[1];
+            bz[u] = B[2];
+          }
+        } else {
+          sc[u] = cc[u] && jc[u] >= 0 ? a.spin[desc_of(O[u].c).vbase + jc[u]] : 0;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < kOwners; ++u) {
-        const bool f = cc[u] && owner_survives(desc_of, step, O[u], jc[u], mc[u], kc[u], sc[u]);
+        bool f;
+        if constexpr (Heis)
+          f = cc[u] && owner_survives_heis(a, desc_of, step, O[u], jc[u], mc[u], kc[u], xc[u], yc[u], bx[u], by[u],
+                                           bz[u], tally);
+        else
+          f = cc[u] && owner_survives(desc_of, step, O[u], jc[u], mc[u], kc[u], sc[u]);
         O[u].ns = append(f, O[u].g, O[u].v, jc[u], mc[u], O[u].ns);
       }
       // an ended owner's survivor count starts its row's cursor for the partners
@@ -817,7 +907,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
           a.fill[O[u].g] = O[u].ns;
           O[u].ns = 0;
         }
-        owner_take(a, desc_of, O[u], !O[u].live && pool, pool, &s_next, ch0, ch1, c_uni);
+        owner_take<Heis>(a, desc_of, O[u], !O[u].live && pool, pool, &s_next, ch0, ch1, c_uni);
       }
     }
   };
@@ -2499,14 +2589,137 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   return true;
 }
 
+// Metropolis on H' (Eq. 4) for Heisenberg spins, colour class by colour class with a
+// full device barrier between classes (plain loads and stores of the spins).  Site v
+// proposes S' uniform on the sphere (Marsaglia, Philox(step, v, s, HP + 256 k)); its
+// local energy is -J S . h + the sum of Vbar over its bonds in row order, h the sum of
+// its lattice neighbours (+x, -x, +y, -y), Vbar = V - T log(1 - P) with
+// 1 - P = -expm1(beta (V - V^max)) (+inf where that is not positive); dE = E(S') - E(S)
+// is accepted when dE <= 0, else when u < exp(-beta dE), u from Philox(step, v, s, HA).
+__device__ __forceinline__ double heis_vbar(const ChainDesc& d, double ax, double ay, double az, double bx,
+                                            double by, double bz, int dx, int dy, double Jm) {
+  const double V = heis_pair(ax, ay, az, bx, by, bz, dx, dy, Jm);
+  const double g = -expm1(d.beta * (V - Jm));
+  return g > 0.0 ? V - d.T * log(g) : static_cast<double>(INFINITY);
+}
+
+__device__ __forceinline__ bool phase_sweep_heis(const StepArgs& a, uint32_t step, int32_t* lds_list) {
+  __shared__ int32_t hoff[SCO_MAXQ + 1];
+  __shared__ int32_t hfill[SCO_MAXQ];
+  const int qmax = static_cast<int>(a.sync->qmax);
+  const int64_t S = ((a.G + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+  const int64_t r0 = min(static_cast<int64_t>(blockIdx.x) * S, a.G);
+  const int64_t r1 = min(r0 + S, a.G);
+  const int tid = static_cast<int>(threadIdx.x);
+  int32_t* const lst = r1 - r0 <= kListCap ? lds_list : reinterpret_cast<int32_t*>(a.rec) + r0;
+  Tally tally(r0 < r1 ? a.chunk_chain[r0 >> SCO_CHUNK_SHIFT] : 0);
+  uint32_t acc0 = 0u;  // accepted flips of the block's first chain (tally.c0)
+  for (int k = tid; k <= qmax; k += kBlock) hoff[k] = 0;
+  __syncthreads();
+  // colour buckets of the block's sites (block-local offsets)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t g = r0 + tid; g < r1; g += kBlock) {
+      const ChainDesc& d = a.cd[a.chunk_chain[g >> SCO_CHUNK_SHIFT]];
+      if (static_cast<int>(g - d.vbase) >= d.N) continue;
+      const int col = a.color[g];
+      if (col >= qmax) {  // cannot happen after a complete colouring
+        if (pass == 0) set_flag(a.sync, SCO_FLAG_PALETTE);
+        continue;
+      }
+      if (pass == 0) atomicAdd(&hoff[col + 1], 1);
+      else lst[hoff[col] + atomicAdd(&hfill[col], 1)] = static_cast<int32_t>(g - r0);
+    }
+    __syncthreads();
+    if (pass == 0) {
+      if (tid == 0)
+        for (int k = 0; k < qmax; ++k) hoff[k + 1] += hoff[k];
+      for (int k = tid; k < qmax; k += kBlock) hfill[k] = 0;
+      __syncthreads();
+    }
+  }
+  for (int s = 0; s < a.nsw_max; ++s) {
+    for (int cc = 0; cc < qmax; ++cc) {
+      for (int k = hoff[cc] + tid; k < hoff[cc + 1]; k += kBlock) {
+        const int64_t g = r0 + lst[k];
+        const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+        const ChainDesc& d = a.cd[c];
+        const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
+        if (s >= nsw) continue;
+        const int v = static_cast<int>(g - d.vbase);
+        double px, py, pz;
+        if (!sphere_point(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_HP, d.seed, d.chain_id,
+                          px, py, pz))
+          continue;
+        const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
+        int nb[4];
+        nn_sites(x, y, d.L, d.periodic, nb);
+        double hx = 0.0, hy = 0.0, hz = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (nb[t] >= 0) {
+            const double* B = a.spin3 + 3 * (d.vbase + nb[t]);
+            hx += B[0];
+            hy += B[1];
+            hz += B[2];
+          }
+        double* Sp = a.spin3 + 3 * g;
+        const double sx = Sp[0], sy = Sp[1], sz = Sp[2];
+        const double mJ = -(d.twoJ * 0.5);
+        double Eold = mJ * (sx * hx + sy * hy + sz * hz);
+        double Enew = mJ * (px * hx + py * hy + pz * hz);
+        int b0 = a.row_ptr[g], b1 = a.row_ptr[g + 1];
+        row_checked(a, b0, b1);
+        for (int e = b0; e < b1; ++e) {
+          const int m = a.attr[e];
+          const double* B = a.spin3 + 3 * static_cast<int64_t>(a.col[e]);
+          const uint32_t hp = ld_global(&d.hd[m]);
+          const int dx = static_cast<int16_t>(hp & 0xFFFFu), dy = static_cast<int16_t>(hp >> 16);
+          const double Jm = ld_global(&d.J[m]);
+          const double bx = B[0], by = B[1], bz = B[2];
+          Eold += heis_vbar(d, sx, sy, sz, bx, by, bz, dx, dy, Jm);
+          Enew += heis_vbar(d, px, py, pz, bx, by, bz, dx, dy, Jm);
+        }
+        const double dE = Enew - Eold;
+        bool acc = true;
+        if (!(dE <= 0.0)) {
+          const W4 w = philox10(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_HA, d.seed,
+                                d.chain_id);
+          const double u = unit52(w.x, w.y);
+          const double pr = exp(-d.beta * dE);
+          if (fabs(u - pr) < 1e-12) tally.tie(a, c);
+          acc = u < pr;
+        }
+        if (acc) {
+          Sp[0] = px;
+          Sp[1] = py;
+          Sp[2] = pz;
+          if (c == tally.c0) ++acc0;
+          else atomicAdd(&a.st[c].accepted, 1ull);
+        }
+      }
+      if (!grid_barrier(a.sync)) return false;
+    }
+  }
+  tally.flush(a);
+  const unsigned long long ta = block_sum(static_cast<unsigned long long>(acc0));
+  if (tid == 0 && ta && tally.c0 < a.n_chains) atomicAdd(&a.st[tally.c0].accepted, ta);
+  if (blockIdx.x == 0)
+    for (int c = tid; c < a.n_chains; c += kBlock) {
+      const int nsw = a.nsw_override >= 0 ? a.nsw_override : a.cd[c].n_sw;
+      a.st[c].attempts += static_cast<unsigned long long>(a.cd[c].N) * static_cast<unsigned long long>(nsw);
+    }
+  return true;
+}
+
 // ------------------------------------------------------------------ the step
 // Persistent kernel (cooperative launch: every block resident).  `phases` selects
 // steps (1) switching + assembly, (2) colouring, (3) sweeps.  The switching part
 // starts by clearing the degree and cursor arrays and the per-chain counters of the
 // graph; a launch without it checks that the words left by the earlier launches say
 // a complete graph (and colouring) is there.
-template <uint32_t phases>
+template <uint32_t phases, int model>
 __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, PhaseLds& lds, KwShared& ks) {
+  constexpr bool heis = model == SCO_MODEL_HEIS;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   {
@@ -2538,7 +2751,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     }
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 1);
-    phase_switch(a, step, lds.list);
+    phase_switch<heis>(a, step, lds.list);
     mark(a.trace, 2);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
@@ -2589,7 +2802,11 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     }
     mark(a.trace, 20);
     // the sweeps end with a full barrier, so the next step sees every spin
-    if (!phase_sweep(a, step, lds.list)) return false;
+    if constexpr (heis) {
+      if (!phase_sweep_heis(a, step, lds.list)) return false;
+    } else {
+      if (!phase_sweep(a, step, lds.list)) return false;
+    }
     mark(a.trace, 21);
   }
   return true;
@@ -2602,11 +2819,11 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
 // the earlier launches say a complete graph (and colouring) is there.  (Looping over
 // several steps inside one launch was measured to push the fused kernel past its
 // register budget into spills, for a saving of a few microseconds per step.)
-template <uint32_t phases>
+template <uint32_t phases, int model>
 __global__ void __launch_bounds__(kBlock) k_step(const StepArgs a) {
   __shared__ PhaseLds lds;
   __shared__ KwShared ks;
-  step_body<phases>(a, a.step, lds, ks);
+  step_body<phases, model>(a, a.step, lds, ks);
 }
 
 // =================================================================== observables
@@ -2669,6 +2886,77 @@ extern "C" __global__ void k_anneal_acc(const ChainState* __restrict__ st, Annea
   x.bonds += st[c].n_edges;
   x.delta_sco += static_cast<unsigned long long>(st[c].delta_sco);
   x.delta_union += static_cast<unsigned long long>(st[c].delta_union);
+}
+
+// Heisenberg, open lattice: prod[m] = sum over the owners i ascending of the pair
+// energy of displacement m (the order of the reference's sum, so each prod[m] is the
+// same number).
+extern "C" __global__ void k_obs_heis_pairs(const uint32_t* __restrict__ hd, const double* __restrict__ J, int K,
+                                            int L, const double* __restrict__ s3, double* __restrict__ prod) {
+  const int64_t m = gtid();
+  if (m >= K) return;
+  const uint32_t p = hd[m];
+  const int dx = static_cast<int16_t>(p & 0xFFFFu), dy = static_cast<int16_t>(p >> 16);
+  const double Jm = J[m];
+  double em = 0.0;
+  for (int y = 0; y + dy < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const int jx = x + dx;
+      if (jx < 0 || jx >= L) continue;
+      const double* A = s3 + 3 * (static_cast<int64_t>(y) * L + x);
+      const double* B = s3 + 3 * (static_cast<int64_t>(y + dy) * L + jx);
+      em += heis_pair(A[0], A[1], A[2], B[0], B[1], B[2], dx, dy, Jm);
+    }
+  prod[m] = em;
+}
+
+// Heisenberg, per block of 256 sites: the exchange sum over the (+x, +y) pairs and the
+// Eq. (7) sum of [S x (r - r_c) / |r - r_c|]_z, r_c = ((L-1)/2, (L-1)/2); fixed tree order.
+extern "C" __global__ void __launch_bounds__(256)
+    k_obs_heis_site(const double* __restrict__ s3, int L, double* __restrict__ part2) {
+  __shared__ double be[256], bm[256];
+  const int N = L * L;
+  const int v = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  double ex = 0.0, mp = 0.0;
+  if (v < N) {
+    const int y = v / L, x = v - y * L;
+    const double* S = s3 + 3 * static_cast<int64_t>(v);
+    if (x + 1 < L) ex += S[0] * S[3] + S[1] * S[4] + S[2] * S[5];
+    if (y + 1 < L) {
+      const double* U = S + 3 * static_cast<int64_t>(L);
+      ex += S[0] * U[0] + S[1] * U[1] + S[2] * U[2];
+    }
+    const double rx = static_cast<double>(x) - 0.5 * static_cast<double>(L - 1);
+    const double ry = static_cast<double>(y) - 0.5 * static_cast<double>(L - 1);
+    const double d = sqrt(rx * rx + ry * ry);
+    if (d > 0.0) mp = (S[0] * ry - S[1] * rx) / d;
+  }
+  be[threadIdx.x] = ex;
+  bm[threadIdx.x] = mp;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < static_cast<uint32_t>(o)) {
+      be[threadIdx.x] += be[threadIdx.x + o];
+      bm[threadIdx.x] += bm[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = be[0];
+    part2[2 * blockIdx.x + 1] = bm[0];
+  }
+}
+
+extern "C" __global__ void k_obs_heis_site_final(const double* __restrict__ part2, int nparts,
+                                                 double* __restrict__ out2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double e = 0.0, m = 0.0;
+  for (int i = 0; i < nparts; ++i) {
+    e += part2[2 * i];
+    m += part2[2 * i + 1];
+  }
+  out2[0] = e;
+  out2[1] = m;
 }
 
 // Spins of one chain as bit rows: bit x of row y set when s(x, y) = -1; W words a row.
@@ -2837,24 +3125,29 @@ hipError_t table_j(hipStream_t s, const uint32_t* hd, int K, int L, int periodic
 }
 
 hipError_t init_spins(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
-                      const int64_t* src_base, const int8_t* src, int8_t* spin, int64_t G) {
+                      const int64_t* src_base, const int8_t* src, int8_t* spin, double* spin3, int64_t G) {
   hipLaunchKernelGGL(k_init_spins, dim3(static_cast<uint32_t>(G / kBlock)), dim3(kBlock), 0, s, cd,
-                     chunk_chain, src_base, src, spin, G);
+                     chunk_chain, src_base, src, spin, spin3, G);
   return hipGetLastError();
 }
 
-template <uint32_t P>
+template <uint32_t P, int M>
 const void* step_kernel() {
-  return reinterpret_cast<const void*>(&k_step<P>);
+  return reinterpret_cast<const void*>(&k_step<P, M>);
 }
 
-const void* step_kernel_for(uint32_t phases) {
+template <int M>
+const void* step_kernel_of(uint32_t phases) {
   switch (phases) {
-    case PH_SWITCH: return step_kernel<PH_SWITCH>();
-    case PH_COLOR: return step_kernel<PH_COLOR>();
-    case PH_SWEEP: return step_kernel<PH_SWEEP>();
-    default: return step_kernel<PH_SWITCH | PH_COLOR | PH_SWEEP>();
+    case PH_SWITCH: return step_kernel<PH_SWITCH, M>();
+    case PH_COLOR: return step_kernel<PH_COLOR, M>();
+    case PH_SWEEP: return step_kernel<PH_SWEEP, M>();
+    default: return step_kernel<PH_SWITCH | PH_COLOR | PH_SWEEP, M>();
   }
+}
+
+const void* step_kernel_for(uint32_t phases, int model) {
+  return model == SCO_MODEL_HEIS ? step_kernel_of<SCO_MODEL_HEIS>(phases) : step_kernel_of<SCO_MODEL_ISING>(phases);
 }
 
 // co-resident blocks of the step kernels (the smallest over the variants)
@@ -2864,26 +3157,43 @@ int step_max_blocks() {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   int best = 1 << 30;
   const uint32_t variants[4] = {PH_SWITCH, PH_COLOR, PH_SWEEP, PH_SWITCH | PH_COLOR | PH_SWEEP};
-  for (uint32_t ph : variants) {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_kernel_for(ph), kBlock, 0) != hipSuccess) return 0;
-    best = per < best ? per : best;
-  }
+  for (int model : {SCO_MODEL_ISING, SCO_MODEL_HEIS})
+    for (uint32_t ph : variants) {
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_kernel_for(ph, model), kBlock, 0) != hipSuccess)
+        return 0;
+      best = per < best ? per : best;
+    }
   return best * cus;
 }
 
-const void* step_kernel_full() { return step_kernel_for(PH_SWITCH | PH_COLOR | PH_SWEEP); }
+const void* step_kernel_full(int model) { return step_kernel_for(PH_SWITCH | PH_COLOR | PH_SWEEP, model); }
 
-hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks) {
+hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks, int model) {
   StepArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(step_kernel_for(phases), dim3(blocks), dim3(kBlock), args, 0, s);
+  return hipLaunchCooperativeKernel(step_kernel_for(phases, model), dim3(blocks), dim3(kBlock), args, 0, s);
 }
 
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain, const int8_t* spin,
                      const uint16_t* color, unsigned long long* out, unsigned* used, int64_t G) {
   hipLaunchKernelGGL(k_obs_basic, dim3(static_cast<uint32_t>(G / kBlock)), dim3(kBlock), 0, s, cd,
                      chunk_chain, spin, color, out, used, G);
+  return hipGetLastError();
+}
+
+hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& h, const double* spin3,
+                    double* prod, double* part, double* out, double* part2, double* out2) {
+  (void)cd;
+  (void)chain;
+  const double* s3 = spin3 + 3 * h.vbase;
+  hipLaunchKernelGGL(k_obs_heis_pairs, dim3((h.K + 255) / 256), dim3(256), 0, s, h.hd, h.J, h.K, h.L, s3, prod);
+  const int nparts = (h.K + 4095) / 4096;
+  hipLaunchKernelGGL(k_obs_sum_partials, dim3(nparts), dim3(256), 0, s, prod, h.K, part);
+  hipLaunchKernelGGL(k_obs_sum_final, dim3(1), dim3(64), 0, s, part, nparts, out);
+  const int nb = (h.N + 255) / 256;
+  hipLaunchKernelGGL(k_obs_heis_site, dim3(nb), dim3(256), 0, s, s3, h.L, part2);
+  hipLaunchKernelGGL(k_obs_heis_site_final, dim3(1), dim3(64), 0, s, part2, nb, out2);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ def log(msg: str) -> None:
 
 
 def oracle_params(p: dict) -> oracle.ChainParams:
-    keys = ("L", "periodic", "T", "J", "D", "kappa", "n_images", "n_sw", "seed", "chain_id", "coloring")
+    keys = ("L", "periodic", "T", "J", "D", "kappa", "n_images", "n_sw", "seed", "chain_id", "coloring", "model")
     return oracle.ChainParams(**{k: p[k] for k in keys if k in p})
 
 

@@ -1,0 +1,126 @@
+"""The Heisenberg model of Eq. (6) (full dipolar tensor, open lattice) on the GPU
+against the oracle: spins (FP64 3-vectors, bit for bit), CSR and colours after every
+step, energies within 1e-12 relative, M_phi of Eq. (7), integer graph statistics and
+near-tie counts."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.parity import gpu_params, log, oracle_params, step_all
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1503_03295_amd import lib
+
+    lib()
+    yield
+
+
+def heis(L, T, chain_id=0, n_sw=1, seed=1):
+    return dict(workloads.chain(L, False, T, 1.0, chain_id=chain_id, n_sw=n_sw, seed=seed), model=1, edge_factor=32)
+
+
+def run_heis(params, n_steps, schedule=None, first_step=0):
+    from paper_1503_03295_amd import SCO
+
+    gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
+    if schedule:
+        gpu.set_schedule(*schedule)
+    refs = [oracle.OracleChain(oracle_params(p)) for p in params]
+    for c, r in enumerate(refs):
+        np.testing.assert_array_equal(gpu.spins3(c), r.spins3, err_msg=f"initial spins of chain {c}")
+    tolerated = 0
+    for s in range(n_steps):
+        t = first_step + s
+        gpu.step(t)
+        before = [r.observables(dipolar="none")["near_ties"] for r in refs]
+        step_all(refs, t)
+        for c, r in enumerate(refs):
+            diffs = []
+            if not np.array_equal(gpu.spins3(c), r.spins3):
+                diffs.append("spins")
+            rp, col, at, colors = gpu.graph(c)
+            orp, ocol, oat = r.csr()
+            if not (np.array_equal(rp, orp) and np.array_equal(col, ocol) and np.array_equal(at, oat)):
+                diffs.append("csr")
+            if not np.array_equal(colors, r.colors()):
+                diffs.append("colors")
+            if diffs:
+                ties = r.observables(dipolar="none")["near_ties"] - before[c]
+                assert ties > 0, f"chain {c} step {t}: {diffs} differ with no near tie ({params[c]})"
+                log(f"  chain {c} step {t}: {diffs} differ after {ties} near tie(s); resynchronised")
+                tolerated += 1
+                r.spins3 = gpu.spins3(c)
+    go = gpu.observables()
+    for c, r in enumerate(refs):
+        ro = r.observables()
+        g = go[c]
+        for k in ("n_edges", "delta_union", "delta_sco", "q", "colors_used", "kw_levels", "kw_rounds"):
+            assert g[k] == ro[k], (c, k, g[k], ro[k])
+        if tolerated == 0:
+            assert g["near_ties"] == ro["near_ties"], (c, g["near_ties"], ro["near_ties"])
+        for k in ("E", "E_exchange", "E_dipolar"):
+            assert abs(g[k] - ro[k]) <= 1e-12 * max(1.0, abs(ro[k])), (c, k, g[k], ro[k])
+        assert abs(g["m_phi"] - ro["m_phi"]) <= 1e-13, (c, g["m_phi"], ro["m_phi"])
+    return {"gpu": gpu, "refs": refs, "tolerated": tolerated}
+
+
+def test_heisenberg_small_lattices():
+    """Three open lattices in one context (T from 0.3 to 1.2, n_sw up to 3)."""
+    params = [heis(16, 0.5, 0), heis(24, 1.2, 1, n_sw=3), heis(33, 0.3, 2, n_sw=2)]
+    log("heisenberg: 16, 24, 33 open")
+    out = run_heis(params, 12)
+    obs = out["gpu"].counters()
+    log("  bonds " + ", ".join(str(o["n_edges"]) for o in obs) + "; q " + ", ".join(str(o["q"]) for o in obs))
+    assert out["tolerated"] == 0
+    assert all(o["accepted"] > 0 for o in obs)
+
+
+@pytest.mark.parametrize("tile_limit", [0, 128])
+def test_heisenberg_paper_size(tile_limit):
+    """L = 128 open (the lattice of the paper's Fig. 4) at T = 0.5: five steps, the KW
+    levels in LDS tiles or above them device-wide."""
+    params = [heis(128, 0.5, 0, n_sw=2)]
+    log(f"heisenberg L=128, tile_limit={tile_limit}")
+    out = run_heis(params, 5, schedule=(0, tile_limit))
+    assert out["tolerated"] == 0
+
+
+def test_heisenberg_anneal_matches_oracle():
+    """The cooling protocol over a Heisenberg chain: stage energies and M_phi."""
+    from paper_1503_03295_amd import SCO
+
+    p = heis(20, 1.25, 0, n_sw=2)
+    temps = [1.25, 0.85, 0.45]
+    gpu = SCO([gpu_params(p)], device="cuda:0")
+    st = gpu.anneal(temps, 1, 2)
+    ref = oracle.OracleChain(oracle_params(p))
+    rs = oracle.anneal(ref, temps, 1, 2)
+    for k, r in enumerate(rs):
+        g = st[k][0]
+        for key in ("T", "samples", "k_mean", "delta_sco_mean", "delta_union_mean", "acceptance"):
+            assert g[key] == r[key], (k, key, g[key], r[key])
+        assert abs(g["E"] - r["E"]) <= 1e-12 * abs(r["E"])
+    np.testing.assert_array_equal(gpu.spins3(0), ref.spins3)
+
+
+def test_heisenberg_rejects_what_it_does_not_support():
+    from paper_1503_03295_amd import SCO, ChainParams, ScoError, workspace_size
+
+    for bad in (dict(periodic=True), dict(kappa=2.0), dict(precision=1)):
+        kw = dict(L=16, periodic=False, T=1.0, model=1)
+        kw.update(bad)
+        with pytest.raises(ScoError):
+            workspace_size([ChainParams(**kw)])
+    with pytest.raises(ScoError):  # one model per context
+        workspace_size([ChainParams(L=16, periodic=False, T=1.0, model=1), ChainParams(L=16, periodic=False, T=1.0)])
+    g = SCO([ChainParams(L=8, periodic=False, T=1.0, model=1)], device="cuda:0")
+    with pytest.raises(ScoError):
+        g.spins(0)
