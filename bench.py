@@ -9,7 +9,8 @@ the steps replayed as one HIP graph, inputs resident in HBM, HIP events on the
 library's stream.  `roofline` puts that kernel's algorithmic bytes per launch over
 its measured time against the HBM peak.  Extra legs: the three phases as separate
 launches, n_sw = 100, the 64-chain batch, the 9-chain mixed-precision workload (FP64
-vs FP32 + recheck), the annealing schedule and the colouring variants.  The CPU
+vs FP32 + recheck), the annealing schedule, the colouring variants and the paper's
+Heisenberg model at L = 2304.  The CPU
 oracle is timed on a short sample of the same chain (one host thread).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -148,6 +149,35 @@ def anneal_leg(torch, SCO, ChainParams, L=512):
     out = {"L": L, "stages": len(temps), "steps": steps, "n_sw": 100, "ms_total": ms,
            "attempts_per_s": L * L * 100 * steps / (ms / 1e3), "table1_like": pick}
     progress(f"anneal L={L}: {ms:.1f} ms for {steps} steps; {pick}")
+    return out
+
+
+def heisenberg_leg(torch, SCO, ChainParams, L=2304, T=1.25, n_sw=100, warm=3, steps=3):
+    """The paper's own model (Eq. 6, Heisenberg spins, full dipolar tensor, open
+    boundaries) at its size and n_sw: SCO steps timed after a few warm-up steps, with
+    the switched graph's mean and maximum degree (Table 1's <k> and <Delta>; the paper
+    quotes 1.40 and 8.54 at T = 1.25 for equilibrated chains)."""
+    import workloads
+
+    p = dict(workloads.chain(L, False, T, 1.0, n_sw=n_sw), model=1, edge_factor=16)
+    sco = SCO([ChainParams(**p)], device="cuda:0")
+    sco.run(0, warm)
+    ms = time_steps(sco, warm, steps, torch)
+    t = warm + steps
+    sco.switch(t)
+    sco.color()
+    sco.sweep(t, n_sw)
+    ph = sco.phase_times()
+    o = sco.counters()[0]
+    N = L * L
+    out = {"L": L, "T": T, "n_sw": n_sw, "steps": steps, "ms_per_step": ms,
+           "attempts_per_s": N * n_sw / (ms / 1e3),
+           "phase_ms": {"switch": ph[0], "color": ph[1], "sweep": ph[2]},
+           "k_mean": 2.0 * o["n_edges"] / N, "delta_sco": o["delta_sco"], "q": o["q"],
+           "acceptance": o["accepted"] / max(1, o["attempts"])}
+    progress(f"heisenberg L={L} T={T}: {ms:.2f} ms/step, {out['attempts_per_s']:.4g} attempts/s, "
+             f"<k> {out['k_mean']:.3f}, Delta {o['delta_sco']}")
+    sco.close()
     return out
 
 
@@ -307,6 +337,7 @@ def main() -> int:
         extra["workloads"] = legs
         extra["anneal"] = anneal_leg(torch, SCO, ChainParams)
         extra["coloring_variants"] = coloring_leg(torch, SCO, ChainParams, p)
+        extra["heisenberg"] = heisenberg_leg(torch, SCO, ChainParams)
 
     cpu = None
     if not args.no_cpu_baseline:
