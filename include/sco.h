@@ -56,7 +56,8 @@ extern "C" {
 #define SCO_EHIP (-2)      /* a HIP runtime call failed */
 #define SCO_EOVERFLOW (-3) /* surviving bonds exceeded the edge capacity: the step is invalid */
 #define SCO_EINTERNAL (-4) /* an invariant failed: a colouring or sweep launched without a valid
-                              bond graph, or a CSR row outside the edge arrays */
+                              bond graph, a CSR row outside the edge arrays, a KW level above its
+                              round cap, or a check of sco_validate */
 #define SCO_ENOSPC (-5)    /* the workspace is smaller than sco_workspace_size() */
 #define SCO_ETIMEOUT (-6)  /* a bounded device wait ran out (the persistent kernel's blocks were
                               not all resident); the chain state is that before the failed step */
@@ -98,7 +99,8 @@ typedef struct {
   int64_t rechecks;   /* FP32 decisions recomputed in FP64 (precision 1) */
   int64_t flags;      /* device flags seen since the last counter reset: bit 0 edge
                          overflow, bit 1 wait timeout, bit 2 palette overflow,
-                         bit 3 colouring or sweep launched without a valid graph */
+                         bit 3 colouring or sweep launched without a valid graph,
+                         bit 4 a KW level above its round cap */
   int64_t near_ties;  /* decisions whose two compared FP64 numbers lay within 1e-12 of each
                          other: switching targets within 1e-12 relative of C_top or of a
                          bracketing cumulative coupling, Metropolis draws |u - p| < 1e-12
@@ -202,6 +204,36 @@ int sco_set_temperature(sco_ctx* ctx, int chain, double T);
  * equals sco_set_temperature + sco_run stage by stage.  Synchronises after each stage. */
 int sco_anneal(sco_ctx* ctx, const double* temps, int n_stages, int equil_steps, int meas_steps,
                uint64_t first_step, sco_stage* out);
+
+/* Graph statistics of one chain (Sec. 3.2-3.3), synchronising:
+ *   sco_class_sizes      sites per colour of the current colouring into sizes[256]
+ *                        (the per-class work whose imbalance Eq. (9) measures); *n_colors
+ *                        receives 1 + the largest colour in use;
+ *   sco_bond_histogram   surviving bonds of the last switching per half-displacement
+ *                        index, counts[K] (K of sco_get_tables);
+ *   sco_survival_by_distance
+ *                        P_survive(r) of Fig. 5: surviving bonds over owned pairs for each
+ *                        distance r of the table (ascending), into r[], p_survive[] (up to
+ *                        max entries; *n receives the number of distances).
+ * SCO_EINVAL when there is no graph (colouring) yet. */
+int sco_class_sizes(sco_ctx* ctx, int chain, int64_t* sizes, int* n_colors);
+int sco_bond_histogram(sco_ctx* ctx, int chain, int64_t* counts);
+int sco_survival_by_distance(sco_ctx* ctx, int chain, double* r, double* p_survive, int max, int* n);
+
+/* Cap on the synchronous rounds of one KW level (Eq. 5 bounds them by q = Delta + 1):
+ * 0 (the default) checks that bound on every level; a positive cap checks that instead
+ * (a cap below q is a fault injection).  A level above it raises a flag that the next
+ * synchronising call reports as SCO_EINTERNAL (flag bit 4). */
+int sco_set_round_cap(sco_ctx* ctx, int cap);
+
+/* Host check of one chain's invariants (reads the state back; synchronises): bit 0 a
+ * spin not +-1 (Heisenberg: not a finite unit vector), bit 1 the tracked magnetisation
+ * differs from the sum of the spins, bit 2 CSR row offsets out of order or range, bit 3
+ * a row not strictly ascending or with a self or foreign bond, bit 4 a bond without its
+ * reverse (same displacement index), bit 5 a colouring that is not proper on the union
+ * graph or a colour outside the palette.  *failed receives the bits; SCO_EINTERNAL when
+ * any is set. */
+int sco_validate(sco_ctx* ctx, int chain, int64_t* failed);
 
 /* Device flags (SCO_FLAG bits as in sco_obs.flags) of the last flagged launch that a
  * synchronising call consumed, and all flags seen since the last counter reset. */

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libsco.so")
 
 SCO_OK, SCO_EINVAL, SCO_EHIP, SCO_EOVERFLOW, SCO_EINTERNAL, SCO_ENOSPC = 0, -1, -2, -3, -4, -5
 SCO_ETIMEOUT, SCO_EPALETTE = -6, -7
-FLAG_NAMES = {1: "edge overflow", 2: "wait timeout", 4: "palette overflow", 8: "graph state"}
+FLAG_NAMES = {1: "edge overflow", 2: "wait timeout", 4: "palette overflow", 8: "graph state", 16: "KW round cap"}
 
 EXPORTS = [
     "sco_workspace_size", "sco_init", "sco_switch", "sco_color", "sco_sweep", "sco_step", "sco_run",
@@ -17,7 +17,8 @@ EXPORTS = [
     "sco_phase_times", "sco_trace", "sco_trace_read", "sco_reset_counters", "sco_destroy",
     "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags",
     "sco_counters", "sco_run_noalloc", "sco_run_graph", "sco_set_temperature", "sco_anneal",
-    "sco_set_coloring", "sco_get_spins3", "sco_set_spins3",
+    "sco_set_coloring", "sco_get_spins3", "sco_set_spins3", "sco_class_sizes", "sco_bond_histogram",
+    "sco_survival_by_distance", "sco_set_round_cap", "sco_validate",
 ]
 
 
@@ -98,6 +99,11 @@ def lib():
         "sco_set_temperature": ([P, i32, ctypes.c_double], i32),
         "sco_set_coloring": ([P, i32], i32),
         "sco_get_spins3": ([P, i32, P], i32),
+        "sco_class_sizes": ([P, i32, P, ctypes.POINTER(ctypes.c_int)], i32),
+        "sco_bond_histogram": ([P, i32, P], i32),
+        "sco_survival_by_distance": ([P, i32, P, P, i32, ctypes.POINTER(ctypes.c_int)], i32),
+        "sco_set_round_cap": ([P, i32], i32),
+        "sco_validate": ([P, i32, ctypes.POINTER(ctypes.c_int64)], i32),
         "sco_set_spins3": ([P, i32, P], i32),
         "sco_anneal": ([P, ctypes.POINTER(ctypes.c_double), i32, i32, i32, u64, ctypes.POINTER(StageC)], i32),
         "sco_observables": ([P, ctypes.POINTER(ObsC)], i32),

@@ -211,6 +211,64 @@ class SCO:
     def set_schedule(self, blocks: int = 0, tile_limit: int = 0) -> None:
         check(lib().sco_set_schedule(self._h, int(blocks), int(tile_limit)), "sco_set_schedule", self._h)
 
+    # -- graph statistics, checks and the per-step log
+    def class_sizes(self, chain: int = 0) -> np.ndarray:
+        """Sites per colour of the current colouring."""
+        out = np.zeros(256, np.int64)
+        n = ctypes.c_int(0)
+        check(lib().sco_class_sizes(self._h, chain, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)),
+              "sco_class_sizes", self._h)
+        return out[: n.value]
+
+    def bond_histogram(self, chain: int = 0) -> np.ndarray:
+        """Surviving bonds of the last switching per half-displacement index."""
+        K = ctypes.c_int32(0)
+        check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), None, None, None, None, None, None),
+              "sco_get_tables", self._h)
+        out = np.zeros(K.value, np.int64)
+        check(lib().sco_bond_histogram(self._h, chain, out.ctypes.data_as(ctypes.c_void_p)),
+              "sco_bond_histogram", self._h)
+        return out
+
+    def survival_by_distance(self, chain: int = 0):
+        """P_survive(r) of the last switching: (r, p) for every distance of the table."""
+        K = ctypes.c_int32(0)
+        check(lib().sco_get_tables(self._h, chain, ctypes.byref(K), None, None, None, None, None, None),
+              "sco_get_tables", self._h)
+        r = np.zeros(K.value, np.float64)
+        p = np.zeros(K.value, np.float64)
+        n = ctypes.c_int(0)
+        check(lib().sco_survival_by_distance(self._h, chain, r.ctypes.data_as(ctypes.c_void_p),
+                                             p.ctypes.data_as(ctypes.c_void_p), K.value, ctypes.byref(n)),
+              "sco_survival_by_distance", self._h)
+        return r[: n.value], p[: n.value]
+
+    def set_round_cap(self, cap: int) -> None:
+        check(lib().sco_set_round_cap(self._h, int(cap)), "sco_set_round_cap", self._h)
+
+    def validate(self, chain: int = 0) -> int:
+        """Bits of the failed invariant checks (0: all hold); raises on other errors."""
+        bad = ctypes.c_int64(0)
+        rc = lib().sco_validate(self._h, chain, ctypes.byref(bad))
+        if rc not in (_lib.SCO_OK, _lib.SCO_EINTERNAL):
+            check(rc, "sco_validate", self._h)
+        return int(bad.value)
+
+    def run_logged(self, first_step: int, n_steps: int, path: str) -> None:
+        """n_steps steps, one JSON line per step and chain appended to `path`: the step,
+        the chain, and its counters (sco_counters: M, exchange energy, bonds, degrees,
+        palette, colours used, KW levels and rounds, acceptance, rechecks, near ties,
+        flags, M_phi)."""
+        import json
+
+        with open(path, "a") as f:
+            for t in range(first_step, first_step + n_steps):
+                self.step(t)
+                for c, o in enumerate(self.counters()):
+                    rec = {"step": t, "chain": c}
+                    rec.update({k: v for k, v in o.items() if k not in ("E", "E_dipolar", "pad")})
+                    f.write(json.dumps(rec) + "\n")
+
     def set_coloring(self, mode: int) -> None:
         """0 KW rule (2)' (default), 1 checkerboard x KW of the bonds, 2 whole-graph
         basic colour reduction (2)'."""

@@ -61,7 +61,7 @@ struct Layout {
   size_t off_col = 0, off_attr = 0, off_color = 0, off_word = 0, off_rec = 0, off_ecount = 0, off_trace = 0;
   size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
-  size_t off_acc = 0, off_spin3 = 0, off_hpart = 0, off_hres = 0;
+  size_t off_acc = 0, off_spin3 = 0, off_hpart = 0, off_hres = 0, off_csz = 0;
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -155,6 +155,7 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   for (int c = 0; c < n; ++c) maxN = std::max<int64_t>(maxN, static_cast<int64_t>(p[c].L) * p[c].L);
   lay.off_hpart = take(sizeof(double) * 2 * (maxN / 256 + 2));
   lay.off_hres = take(sizeof(double) * 2);
+  lay.off_csz = take(sizeof(unsigned long long) * 256);
   lay.bytes = off;
   return SCO_OK;
 }
@@ -839,6 +840,191 @@ int sco_anneal(sco_ctx* c, const double* temps, int n_stages, int equil_steps, i
     }
   }
   return SCO_OK;
+}
+
+int sco_set_round_cap(sco_ctx* c, int cap) {
+  if (!c || cap < 0) return SCO_EINVAL;
+  c->args.round_cap = cap;
+  return SCO_OK;
+}
+
+int sco_class_sizes(sco_ctx* c, int chain, int64_t* sizes, int* n_colors) {
+  if (!c || chain < 0 || chain >= c->n || !sizes) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  if (fr) return fr;
+  if (c->graph_state < 2) return SCO_EINVAL;  // no colouring of the current graph
+  unsigned long long* d = at<unsigned long long>(c, c->lay.off_csz);
+  HIP_TRY(hipMemsetAsync(d, 0, sizeof(unsigned long long) * 256, c->stream));
+  const ChainDesc& cd = c->cd[chain];
+  HIP_TRY(sco_dev::class_sizes(c->stream, at<uint16_t>(c, c->lay.off_color), cd.vbase, cd.N, d));
+  std::vector<unsigned long long> h(256);
+  HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * 256, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int last = 0;
+  for (int k = 0; k < 256; ++k) {
+    sizes[k] = static_cast<int64_t>(h[k]);
+    if (h[k]) last = k + 1;
+  }
+  if (n_colors) *n_colors = last;
+  return SCO_OK;
+}
+
+int sco_bond_histogram(sco_ctx* c, int chain, int64_t* counts) {
+  if (!c || chain < 0 || chain >= c->n || !counts) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  if (fr) return fr;
+  if (c->graph_state < 1) return SCO_EINVAL;
+  const ChainDesc& cd = c->cd[chain];
+  unsigned long long* d = at<unsigned long long>(c, c->lay.off_prod);  // K entries fit (maxK doubles)
+  HIP_TRY(hipMemsetAsync(d, 0, sizeof(unsigned long long) * cd.K, c->stream));
+  HIP_TRY(sco_dev::bond_hist(c->stream, at<int32_t>(c, c->lay.off_row), at<int32_t>(c, c->lay.off_col),
+                             at<int32_t>(c, c->lay.off_attr), cd.vbase, cd.N, d));
+  HIP_TRY(hipMemcpyAsync(counts, d, sizeof(int64_t) * cd.K, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SCO_OK;
+}
+
+int sco_survival_by_distance(sco_ctx* c, int chain, double* r, double* p_survive, int max, int* n) {
+  if (!c || chain < 0 || chain >= c->n || !n || max < 0) return SCO_EINVAL;
+  const ChainDesc& cd = c->cd[chain];
+  std::vector<int64_t> counts(cd.K);
+  const int rc = sco_bond_histogram(c, chain, counts.data());
+  if (rc) return rc;
+  const int t = c->lay.chain_table[chain];
+  const int L = cd.L, h = L / 2;
+  int k = 0;
+  int64_t cur_r2 = -1;
+  double bonds = 0.0, pairs = 0.0;
+  auto emit = [&]() {
+    if (cur_r2 >= 0 && pairs > 0) {
+      if (k < max) {
+        if (r) r[k] = std::sqrt(static_cast<double>(cur_r2));
+        if (p_survive) p_survive[k] = bonds / pairs;
+      }
+      ++k;
+    }
+  };
+  // the table is sorted by r^2: one bin per distance
+  for (int64_t m = 0; m < cd.K; ++m) {
+    const uint32_t w = c->hd[t][m];
+    const int dx = static_cast<int16_t>(w & 0xFFFFu), dy = static_cast<int16_t>(w >> 16);
+    const int64_t r2 = static_cast<int64_t>(dx) * dx + static_cast<int64_t>(dy) * dy;
+    if (r2 != cur_r2) {
+      emit();
+      cur_r2 = r2;
+      bonds = pairs = 0.0;
+    }
+    // owned pairs of the displacement (the owner rules of the half set)
+    double np;
+    if (cd.periodic) {
+      const bool sc = (dy == 0 && dx == h) || (dy == h && (dx == 0 || dx == h));
+      np = sc ? 0.5 * cd.N : static_cast<double>(cd.N);
+    } else {
+      np = static_cast<double>(L - std::abs(dx)) * static_cast<double>(L - dy);
+    }
+    bonds += static_cast<double>(counts[m]);
+    pairs += np;
+  }
+  emit();
+  *n = k;
+  return SCO_OK;
+}
+
+int sco_validate(sco_ctx* c, int chain, int64_t* failed) {
+  if (!c || chain < 0 || chain >= c->n) return SCO_EINVAL;
+  const int fr = consume_flags(c);
+  if (fr) return fr;
+  const ChainDesc& d = c->cd[chain];
+  const Layout& L = c->lay;
+  const int N = d.N, Ls = d.L;
+  int64_t bad = 0;
+  // spins
+  if (c->model == SCO_MODEL_ISING) {
+    std::vector<int8_t> s(N);
+    std::vector<ChainState> st(c->n);
+    HIP_TRY(hipMemcpyAsync(s.data(), at<int8_t>(c, L.off_spin) + d.vbase, N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    long long m = 0;
+    for (int v = 0; v < N; ++v) {
+      if (s[v] != 1 && s[v] != -1) bad |= 1;
+      m += s[v];
+    }
+    if (m != st[chain].mag) bad |= 2;
+  } else {
+    std::vector<double> s3(3 * static_cast<size_t>(N));
+    HIP_TRY(hipMemcpyAsync(s3.data(), at<double>(c, L.off_spin3) + 3 * d.vbase, sizeof(double) * 3 * N,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int v = 0; v < N; ++v) {
+      const double x = s3[3 * v], y = s3[3 * v + 1], z = s3[3 * v + 2];
+      const double n2 = x * x + y * y + z * z;
+      if (!std::isfinite(n2) || std::fabs(n2 - 1.0) > 1e-12) bad |= 1;
+    }
+  }
+  if (c->graph_state >= 1) {
+    std::vector<int32_t> rp(N + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), at<int32_t>(c, L.off_row) + d.vbase, sizeof(int32_t) * (N + 1),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int32_t e0 = rp[0], e1 = rp[N];
+    bool rows_ok = e0 >= 0 && e1 >= e0 && static_cast<int64_t>(e1) <= 2 * static_cast<int64_t>(L.cap_und);
+    for (int v = 0; v < N && rows_ok; ++v) rows_ok = rp[v + 1] >= rp[v];
+    if (!rows_ok) bad |= 4;
+    std::vector<int32_t> col, attr;
+    if (rows_ok && e1 > e0) {
+      col.resize(e1 - e0);
+      attr.resize(e1 - e0);
+      HIP_TRY(hipMemcpyAsync(col.data(), at<int32_t>(c, L.off_col) + e0, sizeof(int32_t) * (e1 - e0),
+                             hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipMemcpyAsync(attr.data(), at<int32_t>(c, L.off_attr) + e0, sizeof(int32_t) * (e1 - e0),
+                             hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      for (auto& x : col) x -= static_cast<int32_t>(d.vbase);
+      for (int v = 0; v < N; ++v)
+        for (int e = rp[v] - e0; e < rp[v + 1] - e0; ++e) {
+          const int u = col[e];
+          if (u < 0 || u >= N || u == v || attr[e] < 0 || attr[e] >= d.K ||
+              (e > rp[v] - e0 && col[e - 1] >= u)) {
+            bad |= 8;
+            continue;
+          }
+          // the reverse direction, with the same displacement index
+          const int a0 = rp[u] - e0, a1 = rp[u + 1] - e0;
+          const auto it = std::lower_bound(col.begin() + a0, col.begin() + a1, v);
+          if (it == col.begin() + a1 || *it != v || attr[it - col.begin()] != attr[e]) bad |= 16;
+        }
+    }
+    if (c->graph_state >= 2 && rows_ok) {
+      std::vector<uint16_t> cl(N);
+      std::vector<ChainState> st(c->n);
+      HIP_TRY(hipMemcpyAsync(cl.data(), at<uint16_t>(c, L.off_color) + d.vbase, sizeof(uint16_t) * N,
+                             hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
+                             c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      const int palette = c->args.coloring == SCO_COLOR_CHECKER ? 2 * st[chain].q : st[chain].q;
+      for (int v = 0; v < N; ++v) {
+        if (cl[v] >= palette) bad |= 32;
+        const int x = v % Ls, y = v / Ls;
+        int nb[4] = {-1, -1, -1, -1};
+        if (d.periodic) {
+          nb[0] = y * Ls + (x + 1) % Ls;
+          nb[2] = ((y + 1) % Ls) * Ls + x;
+        } else {
+          if (x + 1 < Ls) nb[0] = v + 1;
+          if (y + 1 < Ls) nb[2] = v + Ls;
+        }
+        for (int t = 0; t < 4; ++t)
+          if (nb[t] >= 0 && cl[nb[t]] == cl[v]) bad |= 32;
+        for (int e = rp[v] - e0; e < rp[v + 1] - e0 && !col.empty(); ++e)
+          if (col[e] >= 0 && col[e] < N && cl[col[e]] == cl[v]) bad |= 32;
+      }
+    }
+  }
+  if (failed) *failed = bad;
+  return bad ? SCO_EINTERNAL : SCO_OK;
 }
 
 int sco_get_flags(sco_ctx* c, int64_t* last, int64_t* seen) {

@@ -27,7 +27,7 @@ enum { SCO_TAG_INIT = 1, SCO_TAG_SW = 2, SCO_TAG_TH = 3, SCO_TAG_MC = 4, SCO_TAG
 // the full dipolar tensor (open lattices)
 enum { SCO_MODEL_ISING = 0, SCO_MODEL_HEIS = 1 };
 
-enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4, SCO_FLAG_STATE = 8 };
+enum { SCO_FLAG_OVERFLOW = 1, SCO_FLAG_TIMEOUT = 2, SCO_FLAG_PALETTE = 4, SCO_FLAG_STATE = 8, SCO_FLAG_ROUNDS = 16 };
 
 // colouring of step (2): KW with rule (2)' on the union graph; the checkerboard product
 // 2 c + ((x + y) mod 2) of a KW colouring c of the bonds alone; basic colour reduction
@@ -118,6 +118,7 @@ struct StepArgs {
   uint32_t step;
   int32_t tile_limit;     // sites of a KW tile, <= SCO_TILE_MAX (a schedule choice)
   int32_t coloring;       // SCO_COLOR_KW, SCO_COLOR_CHECKER or SCO_COLOR_BCR
+  int32_t round_cap;      // KW rounds allowed per level: 0 = the palette size q (Eq. 5)
 };
 
 #define SCO_TRACE_SLOTS 512
@@ -144,6 +145,11 @@ hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_ch
                      unsigned* used, int64_t G);
 // st[c].mag = out[2 c] (the spin sums of obs_basic) for every chain
 hipError_t set_mag(hipStream_t s, ChainState* st, const unsigned long long* out, int n);
+// colour class sizes of one chain into out[256] (added to)
+hipError_t class_sizes(hipStream_t s, const uint16_t* color, int64_t vbase, int N, unsigned long long* out);
+// surviving bonds per displacement index of one chain into counts[K] (added to)
+hipError_t bond_hist(hipStream_t s, const int32_t* row_ptr, const int32_t* col, const int32_t* attr, int64_t vbase,
+                     int N, unsigned long long* counts);
 // acc[c] += this step's |M|, M^2, directed bonds and maximum degrees
 hipError_t anneal_acc(hipStream_t s, const ChainState* st, AnnealAcc* acc, int n);
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L,

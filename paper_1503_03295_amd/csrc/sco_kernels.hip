@@ -21,6 +21,7 @@
 // the last bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "sco_internal.h"
@@ -1724,6 +1725,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       else run_classes(ColorSet{});
       __syncthreads();
       if (threadIdx.x == 0 && t_rounds > 0) atomicMax(&a.st[c].kw_rounds[p], t_rounds);
+      // Eq. (5): a level takes at most q rounds (or the cap the host set)
+      if (threadIdx.x == 0 && t_rounds > (a.round_cap > 0 ? a.round_cap : q)) set_flag(a.sync, SCO_FLAG_ROUNDS);
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 40 + p);
     }
     const uint32_t tag = static_cast<uint32_t>(P) << 18;
@@ -2036,8 +2039,11 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
     else run_level(ColorSet{}, lds_list);
     // the level ends with a full barrier that also publishes the colours
     if (!grid_barrier(a.sync)) return false;
-    for (int c = tid; c < nch; c += kBlock)
+    for (int c = tid; c < nch; c += kBlock) {
       if (brounds[c] > 0) atomicMax(&a.st[c].kw_rounds[p], brounds[c]);
+      // Eq. (5): a level takes at most q rounds (or the cap the host set)
+      if (brounds[c] > (a.round_cap > 0 ? a.round_cap : ks.kc[c].q)) set_flag(a.sync, SCO_FLAG_ROUNDS);
+    }
     mark(a.trace, 100 + p);
   }
   return true;
@@ -2865,6 +2871,32 @@ extern "C" __global__ void __launch_bounds__(kBlock)
     atomicOr(&used[c * SCO_QWORDS + threadIdx.x], s_used[threadIdx.x]);
 }
 
+// Colour class sizes of one chain: per-block LDS histogram, one atomic per bin.
+extern "C" __global__ void __launch_bounds__(256)
+    k_class_sizes(const uint16_t* __restrict__ color, int64_t vbase, int N, unsigned long long* __restrict__ out) {
+  __shared__ unsigned int h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int v = static_cast<int>(blockIdx.x * 256 + threadIdx.x); v < N; v += static_cast<int>(gridDim.x * 256)) {
+    const int k = color[vbase + v];
+    if (k < 256) atomicAdd(&h[k], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&out[threadIdx.x], static_cast<unsigned long long>(h[threadIdx.x]));
+}
+
+// Surviving bonds per displacement index of one chain: each undirected bond once, from
+// the row of its smaller site.
+extern "C" __global__ void k_bond_hist(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                       const int32_t* __restrict__ attr, int64_t vbase, int N,
+                                       unsigned long long* __restrict__ counts) {
+  const int64_t v = gtid();
+  if (v >= N) return;
+  const int64_t g = vbase + v;
+  for (int e = row_ptr[g]; e < row_ptr[g + 1]; ++e)
+    if (col[e] > g) atomicAdd(&counts[attr[e]], 1ull);
+}
+
 // st[c].mag from the spin sums of k_obs_basic (after the spins were set from outside).
 extern "C" __global__ void k_set_mag(ChainState* __restrict__ st, const unsigned long long* __restrict__ out,
                                      int n) {
@@ -3194,6 +3226,18 @@ hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDe
   const int nb = (h.N + 255) / 256;
   hipLaunchKernelGGL(k_obs_heis_site, dim3(nb), dim3(256), 0, s, s3, h.L, part2);
   hipLaunchKernelGGL(k_obs_heis_site_final, dim3(1), dim3(64), 0, s, part2, nb, out2);
+  return hipGetLastError();
+}
+
+hipError_t class_sizes(hipStream_t s, const uint16_t* color, int64_t vbase, int N, unsigned long long* out) {
+  const int nb = std::min(1024, (N + 255) / 256);
+  hipLaunchKernelGGL(k_class_sizes, dim3(nb), dim3(256), 0, s, color, vbase, N, out);
+  return hipGetLastError();
+}
+
+hipError_t bond_hist(hipStream_t s, const int32_t* row_ptr, const int32_t* col, const int32_t* attr, int64_t vbase,
+                     int N, unsigned long long* counts) {
+  hipLaunchKernelGGL(k_bond_hist, dim3((N + 255) / 256), dim3(256), 0, s, row_ptr, col, attr, vbase, N, counts);
   return hipGetLastError();
 }
 
