@@ -581,6 +581,9 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   a.nchunks = static_cast<int32_t>(L.nchunks);
   a.n_chains = n_chains;
   a.cap_und = L.cap_und;
+  a.any_fp32 = 0;
+  for (int ci = 0; ci < n_chains; ++ci)
+    if (params[ci].precision == 1) a.any_fp32 = 1;
   const int maxb = sco_dev::step_max_blocks();
   if (maxb <= 0) return fail(SCO_EHIP);
   c->max_blocks = std::min(maxb, SCO_MAX_BLOCKS);

@@ -119,6 +119,7 @@ struct StepArgs {
   int32_t tile_limit;     // sites of a KW tile, <= SCO_TILE_MAX (a schedule choice)
   int32_t coloring;       // SCO_COLOR_KW, SCO_COLOR_CHECKER or SCO_COLOR_BCR
   int32_t round_cap;      // KW rounds allowed per level: 0 = the palette size q (Eq. 5)
+  int32_t any_fp32;       // some chain decides in FP32 with FP64 recheck (precision 1)
 };
 
 #define SCO_TRACE_SLOTS 512

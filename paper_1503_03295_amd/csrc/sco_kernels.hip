@@ -597,6 +597,23 @@ struct Owner {
 // the range belongs to chain c_uni.  Dealing owners from one pool keeps the lanes of
 // a wave (and the waves of a block) busy until the block's sites run out, instead of
 // each lane working through a fixed share whose draw count varies.
+// The fields of owner o at global site g of chain c that follow from the site alone.
+template <bool Heis>
+__device__ __forceinline__ void owner_load(const StepArgs& a, const ChainDesc& d, Owner& o, int64_t g, int c) {
+  o.g = g;
+  o.v = static_cast<int>(g - d.vbase);
+  o.c = c;
+  o.y = idiv_fp(o.v, d.inv_L);
+  o.x = o.v - o.y * d.L;
+  if constexpr (Heis) {
+    o.sx = a.spin3[3 * g];
+    o.sy = a.spin3[3 * g + 1];
+    o.sz = a.spin3[3 * g + 2];
+  } else {
+    o.si = a.spin[g];
+  }
+}
+
 template <bool Heis, class Desc>
 __device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, bool need, bool& pool,
                                            uint32_t* s_next, int ch0, int ch1, int c_uni) {
@@ -622,21 +639,10 @@ __device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_o
         const ChainDesc& d = desc_of(c);
         const int v = static_cast<int>(g - d.vbase);
         if (v < d.N) {  // else chunk padding: ask again
-          o.g = g;
-          o.v = v;
-          o.c = c;
-          o.y = idiv_fp(v, d.inv_L);
-          o.x = v - o.y * d.L;
+          owner_load<Heis>(a, d, o, g, c);
           o.pos = -1;
           o.k = 0;
           o.Cpos = 0.0;
-          if constexpr (Heis) {
-            o.sx = a.spin3[3 * g];
-            o.sy = a.spin3[3 * g + 1];
-            o.sz = a.spin3[3 * g + 2];
-          } else {
-            o.si = a.spin[g];
-          }
           o.ns = 0;
           o.live = true;
           want = false;
@@ -708,7 +714,7 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTabl
 template <class Desc>
 __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& desc_of, const SwitchTables& tb,
                                                 uint32_t step, Owner& o, int& j, int& m, uint32_t& kc,
-                                                Tally& tally, int& ddx, int& ddy) {
+                                                Tally& tally, int& ddx, int& ddy, bool fp32_ok, bool& park) {
   const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -728,7 +734,7 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
   }
   const double u1 = unit52(wlo, whi);
   bool done = false;
-  if (d.precision == 1 && d.fp32_gap) {
+  if (d.precision == 1 && d.fp32_gap && fp32_ok) {
     // -log u rounded through FP32 (u to float: 2^-24 relative; logf: about one ulp;
     // the product: two roundings) stays within inv_rate (2^-24 + 2^-22 E) of the exact
     // gap; tol takes four times that, plus the rounding of the FP64 sums.  fp32_gap
@@ -745,7 +751,13 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
       m = table_search(d, tb, target, o.pos);
       done = tb.c_at(d, m) >= target + tol && (m == o.pos + 1 || tb.c_at(d, m - 1) < target - tol);
     }
-    if (!done) tally.recheck(a, o.c);
+    if (!done) {
+      // the owner is parked and finishes its scan in FP64 after the block's pool
+      // (the draw is not consumed)
+      tally.recheck(a, o.c);
+      park = true;
+      return false;
+    }
   }
   if (!done) {
     const double target = o.Cpos + (-log(u1)) * d.inv_rate;
@@ -815,15 +827,19 @@ __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t ste
 // and append); its count is written to the entry of the range's first chunk.
 template <bool Heis>
 __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, int32_t* lds_raw) {
-  __shared__ uint32_t s_count, s_next;
+  __shared__ uint32_t s_count, s_next, s_park, s_ptake;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
   const uint32_t e_base = static_cast<uint32_t>(ch0) * cap_chunk;
   const uint32_t cap_blk = static_cast<uint32_t>(ch1 - ch0) * cap_chunk;
-  if (threadIdx.x == 0) s_count = s_next = 0;
+  if (threadIdx.x == 0) s_count = s_next = s_park = s_ptake = 0;
   __syncthreads();
   const uint32_t lane = lane_id();
+  // owners parked by an FP32 draw that needs FP64 (three int4 each, in the block's
+  // share of the bucket records, which the switching does not use)
+  int4* const parked = a.rec + (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT);
+  const uint32_t park_cap = (static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT) / 3u;
   // returns the owner's count of stored survivors after this append
   auto append = [&](bool f, int64_t g, int v, int j, int m, int ns) -> int {
     const uint64_t mask = __ballot(f);
@@ -849,13 +865,52 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
   };
   Tally tally(ch0 < ch1 ? a.chunk_chain[ch0] : 0);
   auto run = [&](const auto& desc_of, const SwitchTables& tb, int c_uni) {
+  // phase 0: the block's owners from its pool (FP32 draws where the chain allows);
+  // phase 1: the parked owners, every draw in FP64
+  for (int phase = 0; phase < 2; ++phase) {
+    const bool fp32_ok = phase == 0;
+    uint32_t np = 0;
+    if (phase == 1) {
+      __syncthreads();
+      np = min(s_park, park_cap);
+      if (np == 0) break;  // block-uniform
+    }
     bool pool = true;
     Owner O[kOwners];
+    // the next parked owner for each lane that asks (one LDS atomic per wave)
+    auto take_parked = [&](Owner& o, bool need) {
+      const uint64_t m = __ballot(need);
+      if (m == 0) return;
+      const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+      uint32_t base = 0;
+      if (static_cast<int>(lane) == leader) base = atomicAdd(&s_ptake, static_cast<uint32_t>(__popcll(m)));
+      base = __shfl(base, leader);
+      if (!need) return;
+      const uint32_t idx = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+      if (idx >= np) {
+        o.live = false;
+        pool = false;
+        return;
+      }
+      const int4 e0 = parked[3 * idx], e1 = parked[3 * idx + 1], e2 = parked[3 * idx + 2];
+      owner_load<Heis>(a, desc_of(e0.y), o, e0.x, e0.y);
+      o.pos = e0.z;
+      o.k = static_cast<uint32_t>(e0.w);
+      o.Cpos = __hiloint2double(e1.y, e1.x);
+      o.slo = static_cast<uint32_t>(e1.z);
+      o.shi = static_cast<uint32_t>(e1.w);
+      o.ns = e2.x;
+      o.live = true;
+    };
+    auto take = [&](Owner& o, bool need) {
+      if (phase == 0) owner_take<Heis>(a, desc_of, o, need, pool, &s_next, ch0, ch1, c_uni);
+      else take_parked(o, need);
+    };
 #pragma unroll
     for (int u = 0; u < kOwners; ++u) {
       O[u].ns = 0;
       O[u].live = false;
-      owner_take<Heis>(a, desc_of, O[u], pool, pool, &s_next, ch0, ch1, c_uni);
+      take(O[u], pool);
     }
     auto any_live = [&]() {
       bool l = false;
@@ -875,7 +930,24 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         mc[u] = 0;
         kc[u] = 0;
         xc[u] = yc[u] = 0;
-        cc[u] = O[u].live && owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u]);
+        bool park = false;
+        cc[u] = O[u].live &&
+                owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], fp32_ok, park);
+        if (park) {
+          const uint32_t idx = atomicAdd(&s_park, 1u);
+          if (idx < park_cap) {  // saved: the lane takes another owner
+            const Owner& o = O[u];
+            parked[3 * idx] = make_int4(static_cast<int32_t>(o.g), o.c, o.pos, static_cast<int32_t>(o.k));
+            parked[3 * idx + 1] = make_int4(__double2loint(o.Cpos), __double2hiint(o.Cpos), static_cast<int32_t>(o.slo),
+                                            static_cast<int32_t>(o.shi));
+            parked[3 * idx + 2] = make_int4(o.ns, 0, 0, 0);
+            O[u].live = false;
+            O[u].ns = 0;
+          } else {  // no room: this draw in FP64 now
+            bool again = false;
+            cc[u] = owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], false, again);
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < kOwners; ++u) {
@@ -908,9 +980,10 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
           a.fill[O[u].g] = O[u].ns;
           O[u].ns = 0;
         }
-        owner_take<Heis>(a, desc_of, O[u], !O[u].live && pool, pool, &s_next, ch0, ch1, c_uni);
+        take(O[u], !O[u].live && pool);
       }
     }
+  }
   };
   if (ch0 < ch1) {
     // the chunks of a block usually belong to one chain: its descriptor is then
@@ -2229,6 +2302,14 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
   const bool local_cd = c_hi - c_lo < kLocalChains;
   Tally tally(c_lo);
+  // FP32 decisions that need FP64 are queued (list positions) and taken after the
+  // class's main pass, where they run in dense waves: deciding them in line would make
+  // nearly every wave run both paths.  The queue lives in the block's share of the
+  // survivor-rank array, which the sweeps do not use.
+  __shared__ uint32_t s_rq;
+  const uint32_t rq_cap = a.cap_und / gridDim.x;
+  int32_t* const rq = a.er + static_cast<int64_t>(blockIdx.x) * rq_cap;
+  if (tid == 0) s_rq = 0u;
   // the block's flip counts into the chain states (accepted flips, magnetisation)
   auto flush_flips = [&]() {
     __syncthreads();
@@ -2389,6 +2470,49 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
       __syncthreads();
     }
 
+    // the FP64 decision of one soft-bond site (local field NN first, then the bonds in
+    // row order), also the recheck of the FP32 form
+    auto fp64_decision = [&](const ChainDesc& d, int c, int v, int ns, int svv, int b0, int b1,
+                             uint32_t sweep) -> bool {
+      double h = d.twoJ * static_cast<double>(ns);
+      for (int t = b0; t < b1; ++t) {
+        const double dm = ld_global(&d.delta[a.attr[t]]);
+        h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
+      }
+      const double dE = svv > 0 ? h : -h;
+      if (dE <= 0.0) return true;
+      const W4 w = philox10_wide(step, static_cast<uint32_t>(v), sweep, SCO_TAG_MC, d.seed, d.chain_id);
+      const double u = unit52(w.x, w.y);
+      const double pr = exp(d.neg_beta * dE);
+      if (fabs(u - pr) < 1e-12) tally.tie(a, c);
+      return u < pr;
+    };
+    // the decision inputs of one site: the lattice neighbours' spin sum, its spin, its row
+    auto site_inputs = [&](int64_t g, const ChainDesc& d, int& ns, int& svv, int& b0, int& b1) {
+      const int v = static_cast<int>(g - d.vbase);
+      const int y = idiv_fp(v, d.inv_L), x = v - y * d.L;
+      int nb[4];
+      nn_sites(x, y, d.L, d.periodic, nb);
+      ns = 0;
+      if constexpr (staged) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (nb[t] >= 0) {
+            int dv = nb[t] - v;
+            dv = dv > tl_N / 2 ? dv - tl_N : (dv < -(tl_N / 2) ? dv + tl_N : dv);
+            ns += (tile[v + dv - tl_base] & 1) ? 1 : -1;
+          }
+        svv = (tile[v - tl_base] & 1) ? 1 : -1;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (nb[t] >= 0) ns += ld_relaxed(&a.spin[d.vbase + nb[t]]);
+        svv = ld_relaxed(&a.spin[g]);
+      }
+      b0 = a.row_ptr[g];
+      b1 = a.row_ptr[g + 1];
+      row_checked(a, b0, b1);
+    };
     for (int s = 0; s < a.nsw_max; ++s) {
       for (int cc = 0; cc < qmax; ++cc) {
         const int k0 = boff[cc], k1 = boff[cc + 1];
@@ -2480,7 +2604,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                 }
               }
             } else {
-              bool done = false;
+              bool done = false, deferred = false;
               if (d.precision == 1) {
                 // FP32 local field.  Each term carries the rounding of delta to FP32 and
                 // each addition one more, so |dE32 - dE| <= 2 (n + 1) 2^-24 sum|terms|;
@@ -2517,26 +2641,17 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
                     done = true;
                   }
                 }
-                if (!done) tally.recheck(a, c);
-              }
-              if (!done) {
-                double h = d.twoJ * static_cast<double>(nsum[r]);
-                for (int t = q0[r]; t < q1[r]; ++t) {
-                  const double dm = ld_global(&d.delta[a.attr[t]]);
-                  h = ld_relaxed(&a.spin[a.col[t]]) > 0 ? h - dm : h + dm;
-                }
-                const double dE = sv[r] > 0 ? h : -h;
-                if (dE <= 0.0) {
-                  acc[r] = true;
-                } else {
-                  const W4 w = philox10_wide(step, static_cast<uint32_t>(v), static_cast<uint32_t>(s), SCO_TAG_MC,
-                                        d.seed, d.chain_id);
-                  const double u = unit52(w.x, w.y);
-                  const double pr = exp(d.neg_beta * dE);
-                  if (fabs(u - pr) < 1e-12) tally.tie(a, c);
-                  acc[r] = u < pr;
+                if (!done) {
+                  tally.recheck(a, c);
+                  const uint32_t qi = atomicAdd(&s_rq, 1u);
+                  if (qi < rq_cap) {
+                    rq[qi] = kb + r * kBlock + tid;
+                    deferred = true;
+                  }
                 }
               }
+              if (!done && !deferred)
+                acc[r] = fp64_decision(d, c, v, nsum[r], sv[r], q0[r], q1[r], static_cast<uint32_t>(s));
             }
             if (acc[r]) {
               st_relaxed(&a.spin[g], static_cast<int8_t>(-sv[r]));
@@ -2557,6 +2672,28 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
               atomicAdd(&bacc[c], sv[r] > 0 ? 1ull : 1ull << 32);
             }
           }
+        }
+        if (a.any_fp32) {
+          // the queued FP64 rechecks of the class (their neighbours are in other classes,
+          // so the order of the decisions does not matter)
+          __syncthreads();
+          const uint32_t nq = min(s_rq, rq_cap);
+          for (uint32_t i = tid; i < nq; i += kBlock) {
+            const int k = rq[i];
+            const int64_t g = r0 + lst[k];
+            const int c = c_lo == c_hi ? c_lo : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+            const ChainDesc& d = desc(c);
+            int ns, svv, b0, b1;
+            site_inputs(g, d, ns, svv, b0, b1);
+            const int v = static_cast<int>(g - d.vbase);
+            if (fp64_decision(d, c, v, ns, svv, b0, b1, static_cast<uint32_t>(s))) {
+              st_relaxed(&a.spin[g], static_cast<int8_t>(-svv));
+              if constexpr (staged) tile[v - tl_base] ^= 1;
+              atomicAdd(&bacc[c], svv > 0 ? 1ull : 1ull << 32);
+            }
+          }
+          __syncthreads();
+          if (tid == 0) s_rq = 0u;
         }
         // between the classes only the spins change (coherent accesses); the phase ends
         // with a full barrier
