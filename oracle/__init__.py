@@ -101,6 +101,7 @@ def lib():
         L.orc_get_kw_rounds.argtypes = [P, P]; L.orc_get_kw_rounds.restype = None
         L.orc_partner.argtypes = [P, ctypes.c_int, ctypes.c_int]; L.orc_partner.restype = ctypes.c_int
         L.orc_reset_counters.argtypes = [P]; L.orc_reset_counters.restype = None
+        L.orc_ties.argtypes = [P, P, P, ctypes.c_int]; L.orc_ties.restype = ctypes.c_int
         L.orc_set_temperature.argtypes = [P, ctypes.c_double]; L.orc_set_temperature.restype = ctypes.c_int
         L.orc_get_spins3.argtypes = [P, P]; L.orc_get_spins3.restype = None
         L.orc_set_spins3.argtypes = [P, P]; L.orc_set_spins3.restype = None
@@ -260,6 +261,17 @@ class OracleChain:
 
     def reset_counters(self) -> None:
         lib().orc_reset_counters(self._h)
+
+    def ties(self) -> list[tuple[int, int]]:
+        """The near-tie decisions since the last switching as (kind, site): kind 1 a
+        switching decision of owner `site`, kind 2 a sweep decision of `site` (the first
+        256 are listed; a longer list raises)."""
+        kinds = np.zeros(256, np.int32)
+        sites = np.zeros(256, np.int32)
+        n = lib().orc_ties(self._h, _ptr(kinds), _ptr(sites), 256)
+        if n > 256:
+            raise RuntimeError(f"{n} near ties in one step")
+        return list(zip(kinds[:n].tolist(), sites[:n].tolist()))
 
     def colors_rule2(self, whole: bool = False):
         """The colouring with the basic step (2) instead of rule (2)': in every KW level,

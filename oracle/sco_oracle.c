@@ -153,7 +153,20 @@ typedef struct {
   int32_t* color;
   /* counters */
   int64_t accepted, attempts, near_ties;
+  /* the near-tie decisions since the last switching: kind (1 switching, 2 sweep)
+   * and site (the owner, or the swept site); the first 256 are kept */
+  int32_t tie_kind[256], tie_site[256];
+  int32_t n_tie;
 } orc_chain;
+
+static void note_tie(orc_chain* c, int kind, int site) {
+  c->near_ties++;
+  if (c->n_tie < 256) {
+    c->tie_kind[c->n_tie] = kind;
+    c->tie_site[c->n_tie] = site;
+  }
+  c->n_tie++;
+}
 
 static int cmp_disp(const void* a, const void* b) {
   const int32_t* u = (const int32_t*)a;
@@ -373,6 +386,7 @@ static int near(double a, double b) { return fabs(a - b) <= 1e-12 * fabs(b); }
  * survival probability exactly 1 - P_ij as Eq. (1) requires. */
 int orc_switch(orc_chain* c, uint64_t t) {
   c->n_edges = 0;
+  c->n_tie = 0;
   const double Ctop = c->Cm[c->K - 1];
   for (int i = 0; i < c->N; ++i) {
     int pos = -1, k = 0;
@@ -382,7 +396,7 @@ int orc_switch(orc_chain* c, uint64_t t) {
       draw(&c->p, (uint32_t)t, (uint32_t)i, (uint32_t)(k >> 1), TAG_SW, w);
       double u1 = (k & 1) ? orc_u52(w[2], w[3]) : orc_u52(w[0], w[1]);
       double target = Cpos + (-log(u1)) * c->inv_rate;
-      if (near(target, Ctop)) c->near_ties++;
+      if (near(target, Ctop)) note_tie(c, 1, i);
       if (target > Ctop) break;
       int lo = pos + 1, hi = c->K - 1; /* smallest m > pos with C_m >= target */
       while (lo < hi) {
@@ -390,7 +404,7 @@ int orc_switch(orc_chain* c, uint64_t t) {
         if (c->Cm[mid] >= target) hi = mid; else lo = mid + 1;
       }
       int m = lo;
-      if (near(target, c->Cm[m]) || (m - 1 > pos && near(target, c->Cm[m - 1]))) c->near_ties++;
+      if (near(target, c->Cm[m]) || (m - 1 > pos && near(target, c->Cm[m - 1]))) note_tie(c, 1, i);
       int j = partner(c, i, m);
       if (j >= 0 && c->p.model == 1) {
         /* Heisenberg: survive with probability (1 - P_ij) / pbar_m, P_ij of Eq. (2)
@@ -400,7 +414,7 @@ int orc_switch(orc_chain* c, uint64_t t) {
         double u = orc_u52(w2[0], w2[1]);
         double V = pair_energy(c->s3 + 3 * (size_t)i, c->s3 + 3 * (size_t)j, c->hdx[m], c->hdy[m], c->Jm[m]);
         double ratio = expm1(c->beta * (V - c->Jm[m])) / c->hden[m];
-        if (fabs(u - ratio) < 1e-12) c->near_ties++;
+        if (fabs(u - ratio) < 1e-12) note_tie(c, 1, i);
         if (u < ratio) push_survivor(c, i, j, m);
       } else if (j >= 0) {
         int keep = (c->s[i] != c->s[j]);
@@ -735,7 +749,7 @@ static void heis_sweep(orc_chain* c, uint64_t t, int n_sw) {
           draw(&c->p, (uint32_t)t, (uint32_t)v, (uint32_t)s, TAG_HA, w);
           double u = orc_u52(w[0], w[1]);
           double pr = exp(-c->beta * dE);
-          if (fabs(u - pr) < 1e-12) c->near_ties++;
+          if (fabs(u - pr) < 1e-12) note_tie(c, 2, v);
           acc = u < pr;
         }
         if (acc) {
@@ -774,7 +788,7 @@ int orc_sweep(orc_chain* c, uint64_t t, int n_sw) {
           draw(&c->p, (uint32_t)t, (uint32_t)v, (uint32_t)s, TAG_MC, w);
           double u = orc_u52(w[0], w[1]);
           double pr = exp(-c->beta * dE);
-          if (fabs(u - pr) < 1e-12) c->near_ties++;
+          if (fabs(u - pr) < 1e-12) note_tie(c, 2, v);
           acc = u < pr;
         }
         if (acc) { c->s[v] = (int8_t)-c->s[v]; c->accepted++; }
@@ -929,6 +943,17 @@ int orc_sphere_point(const orc_chain* c, uint32_t c0, uint32_t c1, uint32_t c2, 
   return sphere_point(&c->p, c0, c1, c2, tag, out);
 }
 void orc_reset_counters(orc_chain* c) { c->accepted = c->attempts = c->near_ties = 0; }
+
+/* The near-tie decisions since the last switching into kinds[] and sites[] (up to
+ * cap, at most 256 kept); returns how many there were. */
+int orc_ties(const orc_chain* c, int32_t* kinds, int32_t* sites, int cap) {
+  int n = c->n_tie < 256 ? c->n_tie : 256;
+  for (int k = 0; k < n && k < cap; ++k) {
+    kinds[k] = c->tie_kind[k];
+    sites[k] = c->tie_site[k];
+  }
+  return c->n_tie;
+}
 
 /* Per-pair survival counts over n_steps switching passes with the spins held fixed
  * (statistical test helper): counts[i*K + m] += 1 for every survivor (i, m). */

@@ -5,9 +5,10 @@ every compared step the spins, the switched bond graph (CSR rows, neighbours,
 displacement indices), the colours and the integer observables must be identical.
 The only tolerated difference is a decision whose two compared numbers lie within
 1e-12 of each other (the device exp/log may differ from the host's in the last bit):
-the oracle counts such near ties, and a step that differs is accepted only if the
-oracle saw a near tie in it; the oracle then adopts the GPU's spins and the runs
-continue (the count is returned so tests can report it).
+the oracle lists such near ties (kind and site), and a step that differs is accepted
+only if one of that step's tied decisions accounts for the difference (`tie_explains`);
+the oracle then adopts the GPU's spins and the runs continue (the count is returned
+so tests can report and bound it).
 """
 from __future__ import annotations
 
@@ -50,11 +51,36 @@ def compare_state(gpu, ref: oracle.OracleChain, chain: int, what: str, graph: bo
     return diffs
 
 
+def tie_explains(diffs: list[str], ties: list[tuple[int, int]], gpu_spins, ref_spins, n_sw: int,
+                 graph_compared: bool) -> bool:
+    """Whether the oracle's near ties of one step account for `diffs`.  A difference in
+    the bond graph or the colours needs a tied switching decision.  A difference in the
+    spins alone needs a tied sweep decision at one of the differing sites (with n_sw > 1
+    any tied sweep decision, since a later sweep of the step may undo the tied flip), or
+    a tied switching decision when the graph was not compared in that step."""
+    kinds = {k for k, _ in ties}
+    if any(d != "spins" for d in diffs):
+        return 1 in kinds
+    if not graph_compared and 1 in kinds:
+        return True
+    tied = {site for k, site in ties if k == 2}
+    if not tied:
+        return False
+    if n_sw > 1:
+        return True
+    a = np.asarray(gpu_spins).reshape(len(ref_spins), -1)
+    b = np.asarray(ref_spins).reshape(len(ref_spins), -1)
+    differ = set(np.flatnonzero((a != b).any(axis=1)).tolist())
+    return bool(differ & tied)
+
+
 def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_step: int = 0,
-               obs_every: int = 0, schedule: tuple | None = None, counters_every: int = 0) -> dict:
+               obs_every: int = 0, schedule: tuple | None = None, counters_every: int = 0,
+               fenced: bool = False) -> dict:
     """Runs all chains in one GPU context and one oracle chain each; returns counts.
     obs_every: every observable (dipolar energy included); counters_every: the integer
-    observables only; schedule: (blocks, tile_limit) of the GPU context."""
+    observables only; schedule: (blocks, tile_limit) of the GPU context; fenced: full
+    barriers between the sweep's colour classes."""
     from paper_1503_03295_amd import SCO
 
     gpu = SCO([gpu_params(p) for p in params], device="cuda:0")
@@ -63,6 +89,8 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
     modes = {p.get("coloring", 0) for p in params}
     assert len(modes) == 1, "one colouring mode per context"
     gpu.set_coloring(modes.pop())
+    if fenced:
+        gpu.set_fenced_sweeps(True)
     refs = [oracle.OracleChain(oracle_params(p)) for p in params]
     tolerated = 0
     for c, r in enumerate(refs):
@@ -70,19 +98,19 @@ def run_parity(params: list[dict], n_steps: int, graph_every: int = 1, first_ste
     for s in range(n_steps):
         t = first_step + s
         gpu.step(t)
-        before = [r.observables(dipolar="none")["near_ties"] for r in refs]
         step_all(refs, t)
         graph = graph_every > 0 and (s % graph_every == 0 or s == n_steps - 1)
         for c, r in enumerate(refs):
             diffs = compare_state(gpu, r, c, f"step {t}", graph=graph)
             if diffs:
-                ties = r.observables(dipolar="none")["near_ties"] - before[c]
-                if ties == 0:
-                    raise AssertionError(f"chain {c} step {t}: {diffs} differ with no near tie "
-                                         f"in that step (params {params[c]})")
-                log(f"  chain {c} step {t}: {diffs} differ after {ties} near tie(s); resynchronised")
+                ties = r.ties()
+                g = gpu.spins(c)
+                if not tie_explains(diffs, ties, g, r.spins, params[c].get("n_sw", 1), graph):
+                    raise AssertionError(f"chain {c} step {t}: {diffs} differ and no near tie of that step "
+                                         f"accounts for it (ties {ties}, params {params[c]})")
+                log(f"  chain {c} step {t}: {diffs} differ at near tie(s) {ties}; resynchronised")
                 tolerated += 1
-                r.spins = gpu.spins(c)
+                r.spins = g
         if obs_every and (s % obs_every == 0 or s == n_steps - 1):
             compare_observables(gpu, refs, ties=tolerated == 0)
         elif counters_every and (s % counters_every == 0 or s == n_steps - 1):
