@@ -220,6 +220,16 @@ int sco_class_sizes(sco_ctx* ctx, int chain, int64_t* sizes, int* n_colors);
 int sco_bond_histogram(sco_ctx* ctx, int chain, int64_t* counts);
 int sco_survival_by_distance(sco_ctx* ctx, int chain, double* r, double* p_survive, int max, int* n);
 
+/* Barrier between the colour classes of an Ising sweep (Fig. 1 step (3): a class reads
+ * the spins the classes before it wrote).  0 (the default): a light barrier that orders
+ * only the control; the spins are read and written with agent-scope atomics, each by
+ * the one block owning its site, and each wave's stores complete before its block
+ * arrives, with no cache write-back or invalidation.  1: the full barrier with the
+ * agent-scope release/acquire fences of the documented memory model after every class
+ * (slower: the L2 write-back and invalidation run per class).  Same results either way.
+ * Takes effect at the next launch; SCO_EINVAL for other values. */
+int sco_set_fenced_sweeps(sco_ctx* ctx, int on);
+
 /* Cap on the synchronous rounds of one KW level (Eq. 5 bounds them by q = Delta + 1):
  * 0 (the default) checks that bound on every level; a positive cap checks that instead
  * (a cap below q is a fault injection).  A level above it raises a flag that the next

@@ -243,6 +243,11 @@ class SCO:
               "sco_survival_by_distance", self._h)
         return r[: n.value], p[: n.value]
 
+    def set_fenced_sweeps(self, on: bool = True) -> None:
+        """Full release/acquire barriers between the sweep's colour classes (see
+        sco_set_fenced_sweeps); same results, slower."""
+        check(lib().sco_set_fenced_sweeps(self._h, 1 if on else 0), "sco_set_fenced_sweeps", self._h)
+
     def set_round_cap(self, cap: int) -> None:
         check(lib().sco_set_round_cap(self._h, int(cap)), "sco_set_round_cap", self._h)
 

@@ -339,6 +339,11 @@ int temperature_tables(sco_ctx* c, int ci, double T) {
   // an FP32 gap decision is at least inv_rate 2^-20 from the compared table value;
   // it may stand only where no near tie (1e-12 relative) of the FP64 gap can hide
   d.fp32_gap = d.inv_rate * 0x1p-20 > 2e-12 * d.C_top ? 1 : 0;
+  // An owner's first draw u ends it when (-log u) inv_rate > C_top, a near tie when
+  // within 1e-12 C_top.  Below u_first_end the target exceeds C_top (1 + 2e-12) less
+  // the roundings of log, the product and this bound (each under 1e-15 relative), so
+  // the draw ends its owner with certainty and is no near tie.
+  d.u_first_end = std::exp(-(d.C_top * (1.0 + 2e-12)) / d.inv_rate) * (1.0 - 1e-14);
   for (int k = -4; k <= 4; ++k) {
     const double dE = (2.0 * p.J) * static_cast<double>(k);
     d.pacc[k + 4] = dE > 0.0 ? std::exp(-beta * dE) : 2.0;
@@ -842,6 +847,12 @@ int sco_anneal(sco_ctx* c, const double* temps, int n_stages, int equil_steps, i
       o.acceptance = att > 0 ? static_cast<double>(st1[ci].accepted - st0[ci].accepted) / att : 0.0;
     }
   }
+  return SCO_OK;
+}
+
+int sco_set_fenced_sweeps(sco_ctx* c, int on) {
+  if (!c || on < 0 || on > 1) return SCO_EINVAL;
+  c->args.fenced_classes = on;
   return SCO_OK;
 }
 

@@ -53,6 +53,8 @@ struct ChainDesc {
   int32_t fp32_gap;                       // precision 1 may decide switching gaps in FP32
   int32_t model;                          // SCO_MODEL_*
   double T;                               // temperature (Heisenberg pseudo-interactions)
+  double u_first_end;                     // a first draw's uniform below this ends its owner
+                                          // (no candidate and no near tie)
   const double* hden;                     // Heisenberg: expm1(-2 beta J_m) per m (J_m = V^max)
   uint32_t seed, chain_id;
   int32_t hard, precision, n_sw, nguide;
@@ -120,6 +122,7 @@ struct StepArgs {
   int32_t coloring;       // SCO_COLOR_KW, SCO_COLOR_CHECKER or SCO_COLOR_BCR
   int32_t round_cap;      // KW rounds allowed per level: 0 = the palette size q (Eq. 5)
   int32_t any_fp32;       // some chain decides in FP32 with FP64 recheck (precision 1)
+  int32_t fenced_classes; // the sweep's colour classes end with the full (fenced) barrier
 };
 
 #define SCO_TRACE_SLOTS 512

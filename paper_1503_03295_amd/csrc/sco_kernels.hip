@@ -590,13 +590,6 @@ struct Owner {
   bool live;
 };
 
-// Deals the next owner sites of the block's chunks [ch0, ch1) to the lanes that ask
-// (need): one LDS atomic per wave and round, lanes in order; a lane whose site is
-// chunk padding asks again.  A lane that finds the pool empty gets a dead owner and
-// clears `pool`.  Every lane of the wave must call it.  c_uni >= 0: every chunk of
-// the range belongs to chain c_uni.  Dealing owners from one pool keeps the lanes of
-// a wave (and the waves of a block) busy until the block's sites run out, instead of
-// each lane working through a fixed share whose draw count varies.
 // The fields of owner o at global site g of chain c that follow from the site alone.
 template <bool Heis>
 __device__ __forceinline__ void owner_load(const StepArgs& a, const ChainDesc& d, Owner& o, int64_t g, int c) {
@@ -614,59 +607,59 @@ __device__ __forceinline__ void owner_load(const StepArgs& a, const ChainDesc& d
   }
 }
 
-template <bool Heis, class Desc>
-__device__ __forceinline__ void owner_take(const StepArgs& a, const Desc& desc_of, Owner& o, bool need, bool& pool,
-                                           uint32_t* s_next, int ch0, int ch1, int c_uni) {
-  const uint32_t lane = lane_id();
-  const uint32_t total = static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT;
-  bool want = need;
-  while (true) {
-    const uint64_t m = __ballot(want);
-    if (m == 0) break;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    uint32_t base = 0;
-    if (static_cast<int>(lane) == leader) base = atomicAdd(s_next, static_cast<uint32_t>(__popcll(m)));
-    base = __shfl(base, leader);
-    if (want) {
-      const uint32_t idx = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
-      if (idx >= total) {
-        o.live = false;
-        pool = false;
-        want = false;
-      } else {
-        const int64_t g = (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT) + idx;
-        const int c = c_uni >= 0 ? c_uni : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
-        const ChainDesc& d = desc_of(c);
-        const int v = static_cast<int>(g - d.vbase);
-        if (v < d.N) {  // else chunk padding: ask again
-          owner_load<Heis>(a, d, o, g, c);
-          o.pos = -1;
-          o.k = 0;
-          o.Cpos = 0.0;
-          o.ns = 0;
-          o.live = true;
-          want = false;
-        }
-      }
-    }
-  }
-}
+// In-tile bond lists held in LDS: for at most kBondedCap sites with in-tile bonds and
+// kAdjCap entries; a site beyond either reads its row from global memory instead.
+constexpr int kBondedCap = 8192;
+constexpr int kAdjCap = 10240;
+
+// LDS of the colouring and sweep phases: the tile arrays of the local levels, or the
+// bucket list of a block (block-local offsets) in the global levels and the sweeps.
+struct TileLds {
+  uint16_t cr[SCO_TILE_MAX];          // current colour | round of the decision << 8 (0: undecided)
+  uint16_t list[SCO_TILE_MAX / 2];    // pending sites bucketed by colour
+  uint32_t bmask[SCO_TILE_MAX / 32];  // bit i: site i has in-tile bonds
+  uint16_t brank[SCO_TILE_MAX / 32];  // sites with in-tile bonds before word w
+  uint16_t boff[kBondedCap + 1];      // the r-th such site's partners: adj[boff[r], boff[r+1])
+  uint16_t adj[kAdjCap];
+};
+constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
+union alignas(16) PhaseLds {
+  TileLds tile;
+  int32_t list[kListCap];
+};
 
 // The first kSwC entries of a chain's cumulative couplings C and displacements hd,
 // and a guide of kSwGuide buckets, staged in LDS for the switching of a block whose
 // chunks all belong to that chain; nearly every candidate falls among them.  KL = 0:
 // everything is read from global memory.
-constexpr int kSwC = 8192;
+constexpr int kSwC = 5120;
 constexpr int kSwGuide = 1 << 12;
+// the switching's list of owners with a candidate, after its table head or alone
+constexpr int kSwHeadBytes =
+    kSwC * static_cast<int>(sizeof(double) + sizeof(uint32_t)) + (kSwGuide + 1) * static_cast<int>(sizeof(int32_t));
+constexpr uint32_t kSwListCap = static_cast<uint32_t>((static_cast<int>(sizeof(int32_t)) * kListCap - kSwHeadBytes) / 2);
+constexpr uint32_t kSwListCapAll =
+    static_cast<uint32_t>(static_cast<int>(sizeof(int32_t)) * kListCap / 2) < 65536u
+        ? static_cast<uint32_t>(static_cast<int>(sizeof(int32_t)) * kListCap / 2)
+        : 65536u;
+static_assert(kSwListCap >= static_cast<uint32_t>(kBlock), "the switching lists owners after its table head");
 struct SwitchTables {
   const double* C;       // C_0 .. C_{KL-1}
   const uint32_t* hd;    // hd_0 .. hd_{KL-1}
   const int32_t* guide;  // guide[b] = first m with C_m >= b C_top / kSwGuide, b = 0..kSwGuide
   int KL;
   double guide_inv;      // kSwGuide / C_top
+  int klast;             // K - 1 (the bracket's end above the last guide bucket)
   __device__ __forceinline__ double c_at(const ChainDesc& d, int m) const { return m < KL ? C[m] : ld_global(&d.C[m]); }
   __device__ __forceinline__ uint32_t hd_at(const ChainDesc& d, int m) const {
     return m < KL ? hd[m] : ld_global(&d.hd[m]);
+  }
+  // whether the LDS bracket of `target` lies inside the staged entries
+  __device__ __forceinline__ bool in_head(double target) const {
+    if (KL <= 0) return false;
+    int b = static_cast<int>(target * guide_inv);
+    b = b < 0 ? 0 : (b > kSwGuide ? kSwGuide : b);
+    return ((b + 2 <= kSwGuide) ? guide[b + 2] : klast) < KL;
   }
 };
 
@@ -710,11 +703,15 @@ __device__ __forceinline__ int table_search(const ChainDesc& d, const SwitchTabl
 // ends instead (the target passes C_top or the table is exhausted).  With precision
 // 1 the exponential gap is computed in FP32; the FP64 outcome is certain unless the
 // target lies within `tol` of C_top or of the table values it was compared with, and
-// then the gap is recomputed in FP64 (counted in `rechecks`).
+// then the gap is recomputed in FP64 (counted in `rechecks`).  With may_park, a draw
+// that would search the table in global memory (its target beyond the entries staged
+// in LDS: a long bond, about one candidate in a hundred) or recompute in FP64 is not
+// taken: `park` is set and the owner is resumed at the same draw later, so that the
+// wave running it is not held by one lane's chain of dependent global loads.
 template <class Desc>
 __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& desc_of, const SwitchTables& tb,
                                                 uint32_t step, Owner& o, int& j, int& m, uint32_t& kc,
-                                                Tally& tally, int& ddx, int& ddy, bool fp32_ok, bool& park) {
+                                                Tally& tally, int& ddx, int& ddy, bool may_park, bool& park) {
   const ChainDesc& d = desc_of(o.c);
   const int K = d.K;
   if (o.pos >= K - 1) {  // no candidate lies beyond the last table entry
@@ -734,7 +731,7 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
   }
   const double u1 = unit52(wlo, whi);
   bool done = false;
-  if (d.precision == 1 && d.fp32_gap && fp32_ok) {
+  if (d.precision == 1 && d.fp32_gap && may_park) {
     // -log u rounded through FP32 (u to float: 2^-24 relative; logf: about one ulp;
     // the product: two roundings) stays within inv_rate (2^-24 + 2^-22 E) of the exact
     // gap; tol takes four times that, plus the rounding of the FP64 sums.  fp32_gap
@@ -748,6 +745,10 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
       return false;
     }
     if (target + tol <= d.C_top) {
+      if (tb.KL > 0 && !tb.in_head(target + tol)) {  // a long bond: searched later
+        park = true;
+        return false;
+      }
       m = table_search(d, tb, target, o.pos);
       done = tb.c_at(d, m) >= target + tol && (m == o.pos + 1 || tb.c_at(d, m - 1) < target - tol);
     }
@@ -761,6 +762,10 @@ __device__ __forceinline__ bool owner_candidate(const StepArgs& a, const Desc& d
   }
   if (!done) {
     const double target = o.Cpos + (-log(u1)) * d.inv_rate;
+    if (may_park && target <= d.C_top && tb.KL > 0 && !tb.in_head(target)) {  // searched later
+      park = true;
+      return false;
+    }
     if (near_tie(target, d.C_top)) tally.tie(a, o.c);
     if (target > d.C_top) {
       o.live = false;
@@ -827,7 +832,7 @@ __device__ __forceinline__ bool owner_survives(const Desc& desc_of, uint32_t ste
 // and append); its count is written to the entry of the range's first chunk.
 template <bool Heis>
 __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, int32_t* lds_raw) {
-  __shared__ uint32_t s_count, s_next, s_park, s_ptake;
+  __shared__ uint32_t s_count, s_next, s_park, s_ptake, s_nlist;
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
@@ -836,8 +841,8 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
   if (threadIdx.x == 0) s_count = s_next = s_park = s_ptake = 0;
   __syncthreads();
   const uint32_t lane = lane_id();
-  // owners parked by an FP32 draw that needs FP64 (three int4 each, in the block's
-  // share of the bucket records, which the switching does not use)
+  // parked owners (three int4 each, in the block's share of the bucket records, which
+  // the switching does not use)
   int4* const parked = a.rec + (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT);
   const uint32_t park_cap = (static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT) / 3u;
   // returns the owner's count of stored survivors after this append
@@ -864,17 +869,54 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     return ns;
   };
   Tally tally(ch0 < ch1 ? a.chunk_chain[ch0] : 0);
-  auto run = [&](const auto& desc_of, const SwitchTables& tb, int c_uni) {
-  // phase 0: the block's owners from its pool (FP32 draws where the chain allows);
-  // phase 1: the parked owners, every draw in FP64
+  // lst: LDS room for lcap (>= kBlock) owner indices of a segment of the block's owners
+  auto run = [&](const auto& desc_of, const SwitchTables& tb, int c_uni, uint16_t* lst, uint32_t lcap) {
+  const uint32_t total = static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT;
+  // phase 0, segment by segment: every owner's first draw is taken by one lane each
+  // (a convergent pass); an owner whose uniform lies below u_first_end has no
+  // candidate and is done (about half of them), the others are listed and dealt to
+  // the lanes, which run their draws (FP32 where the chain allows);
+  // phase 1: the parked owners (a long bond's table search, or an FP32 draw that
+  // needs FP64), every draw in FP64, the lanes' global searches in flight together
   for (int phase = 0; phase < 2; ++phase) {
-    const bool fp32_ok = phase == 0;
-    uint32_t np = 0;
+   uint32_t s0 = 0;
+   do {
+    const bool may_park = phase == 0;
+    uint32_t np = 0, s1 = total;
     if (phase == 1) {
       __syncthreads();
       np = min(s_park, park_cap);
       if (np == 0) break;  // block-uniform
+    } else {
+      s1 = min(s0 + lcap, total);
+      __syncthreads();  // the previous segment's list is dealt
+      if (threadIdx.x == 0) s_nlist = s_next = 0;
+      __syncthreads();
+      for (uint32_t i0 = s0; i0 < s1; i0 += kBlock) {
+        const uint32_t idx = i0 + threadIdx.x;
+        bool keep = false;
+        if (idx < s1) {
+          const int64_t g = (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT) + idx;
+          const int c = c_uni >= 0 ? c_uni : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+          const ChainDesc& d = desc_of(c);
+          const int v = static_cast<int>(g - d.vbase);
+          if (v < d.N) {  // else chunk padding
+            const W4 r = philox10(step, static_cast<uint32_t>(v), 0u, SCO_TAG_SW, d.seed, d.chain_id);
+            keep = !(unit52(r.x, r.y) < d.u_first_end);
+          }
+        }
+        const uint64_t m = __ballot(keep);
+        if (m != 0) {
+          const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+          uint32_t base = 0;
+          if (static_cast<int>(lane) == leader) base = atomicAdd(&s_nlist, static_cast<uint32_t>(__popcll(m)));
+          base = __shfl(base, leader);
+          if (keep) lst[base + __popcll(m & ((1ull << lane) - 1ull))] = static_cast<uint16_t>(idx - s0);
+        }
+      }
+      __syncthreads();
     }
+    const uint32_t nlist = s_nlist;
     bool pool = true;
     Owner O[kOwners];
     // the next parked owner for each lane that asks (one LDS atomic per wave)
@@ -902,8 +944,33 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       o.ns = e2.x;
       o.live = true;
     };
+    // the next listed owner for each lane that asks (one LDS atomic per wave): lanes
+    // that finish early take more, so a wave is not held by its busiest lane
+    auto take_listed = [&](Owner& o, bool need) {
+      const uint64_t m = __ballot(need);
+      if (m == 0) return;
+      const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+      uint32_t base = 0;
+      if (static_cast<int>(lane) == leader) base = atomicAdd(&s_next, static_cast<uint32_t>(__popcll(m)));
+      base = __shfl(base, leader);
+      if (!need) return;
+      const uint32_t j = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+      if (j >= nlist) {
+        o.live = false;
+        pool = false;
+        return;
+      }
+      const int64_t g = (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT) + s0 + lst[j];
+      const int c = c_uni >= 0 ? c_uni : a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+      owner_load<Heis>(a, desc_of(c), o, g, c);
+      o.pos = -1;
+      o.k = 0;
+      o.Cpos = 0.0;
+      o.ns = 0;
+      o.live = true;
+    };
     auto take = [&](Owner& o, bool need) {
-      if (phase == 0) owner_take<Heis>(a, desc_of, o, need, pool, &s_next, ch0, ch1, c_uni);
+      if (phase == 0) take_listed(o, need);
       else take_parked(o, need);
     };
 #pragma unroll
@@ -932,7 +999,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         xc[u] = yc[u] = 0;
         bool park = false;
         cc[u] = O[u].live &&
-                owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], fp32_ok, park);
+                owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], may_park, park);
         if (park) {
           const uint32_t idx = atomicAdd(&s_park, 1u);
           if (idx < park_cap) {  // saved: the lane takes another owner
@@ -983,6 +1050,8 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         take(O[u], !O[u].live && pool);
       }
     }
+    s0 = s1;
+   } while (phase == 0 && s0 < total);
   }
   };
   if (ch0 < ch1) {
@@ -1004,11 +1073,13 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       if (KL > 0)
         for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = ld_global(&d0.guide[b * gs]);
       __syncthreads();
-      const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs};
-      run([&](int) -> const ChainDesc& { return d0; }, tb, c_lo);
+      const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs, d0.K - 1};
+      uint16_t* lst = reinterpret_cast<uint16_t*>(lg + kSwGuide + 1);
+      run([&](int) -> const ChainDesc& { return d0; }, tb, c_lo, lst, kSwListCap);
     } else {
-      const SwitchTables tb{nullptr, nullptr, nullptr, 0, 0.0};
-      run([&](int c) -> const ChainDesc& { return a.cd[c]; }, tb, -1);
+      const SwitchTables tb{nullptr, nullptr, nullptr, 0, 0.0, 0};
+      run([&](int c) -> const ChainDesc& { return a.cd[c]; }, tb, -1, reinterpret_cast<uint16_t*>(lds_raw),
+          kSwListCapAll);
     }
   }
   __syncthreads();
@@ -1452,30 +1523,7 @@ __device__ __forceinline__ int64_t pending_count(int N, int64_t h) {
 }
 
 
-// In-tile bond lists held in LDS: for at most kBondedCap sites with in-tile bonds and
-// kAdjCap entries; a site beyond either reads its row from global memory instead.
-constexpr int kBondedCap = 8192;
-constexpr int kAdjCap = 10240;
-
-// LDS of the colouring and sweep phases: the tile arrays of the local levels, or the
-// bucket list of a block (block-local offsets) in the global levels and the sweeps.
-struct TileLds {
-  uint16_t cr[SCO_TILE_MAX];          // current colour | round of the decision << 8 (0: undecided)
-  uint16_t list[SCO_TILE_MAX / 2];    // pending sites bucketed by colour
-  uint32_t bmask[SCO_TILE_MAX / 32];  // bit i: site i has in-tile bonds
-  uint16_t brank[SCO_TILE_MAX / 32];  // sites with in-tile bonds before word w
-  uint16_t boff[kBondedCap + 1];      // the r-th such site's partners: adj[boff[r], boff[r+1])
-  uint16_t adj[kAdjCap];
-};
-constexpr int kListCap = static_cast<int>(sizeof(TileLds) / sizeof(int32_t));
 static_assert(kListCap >= kScanLds, "the scan stages a padded tile in the phase LDS");
-static_assert(static_cast<int>(sizeof(int32_t)) * kListCap >=
-                  kSwC * static_cast<int>(sizeof(double) + sizeof(uint32_t)) + (kSwGuide + 1) * static_cast<int>(sizeof(int32_t)),
-              "the switching stages its table head in the phase LDS");
-union alignas(16) PhaseLds {
-  TileLds tile;
-  int32_t list[kListCap];
-};
 
 // Levels 1..P of every tile, in LDS.  Groups up to level P are aligned to the tile,
 // so the same-group neighbours of a tile site are inside the tile; the tile's
@@ -2696,9 +2744,10 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
           if (tid == 0) s_rq = 0u;
         }
         // between the classes only the spins change (coherent accesses); the phase ends
-        // with a full barrier
+        // with a full barrier, and so does every class when the caller asks for the
+        // fenced form
         const bool last = s + 1 == a.nsw_max && cc + 1 == qmax;
-        if (!(last ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
+        if (!(last || a.fenced_classes ? grid_barrier(a.sync) : class_barrier(a.sync))) return false;
         mark(a.trace, 1000 + cc);
       }
       // each half of a block's count stays below 2^32 (flushed every sweep when the

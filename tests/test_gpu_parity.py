@@ -68,6 +68,16 @@ def test_several_sweeps_after_device_wide_levels(kappa):
     log(f"  tolerated near ties: {out['tolerated']}")
 
 
+def test_fenced_sweeps_match_oracle():
+    """The documented release/acquire barrier after every colour class gives the same
+    chains as the light class barrier (a ragged batch, three sweeps per step)."""
+    params = [workloads.chain(256, True, 1.2, 2.0, chain_id=0, n_sw=3),
+              workloads.chain(48, False, 0.9, 1.0, chain_id=1, n_sw=2)]
+    log("fenced sweeps: 256 periodic + 48 open")
+    out = run_parity(params, 4, graph_every=2, counters_every=3, fenced=True)
+    assert out["tolerated"] == 0
+
+
 def test_ragged_batch_of_chains():
     """Chains of different L, boundaries, kappa and n_sw in one launch."""
     params = [workloads.chain(8, True, 2.0, 2.0, chain_id=0, n_sw=2),
