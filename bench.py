@@ -111,6 +111,22 @@ def time_steps(sco, first, steps, torch, graph=True):
     return e0.elapsed_time(e1) / steps
 
 
+def time_both(sco, first, steps, torch, np):
+    """The same steps from the same spins as plain launches and as one HIP-graph
+    replay: (ms graph, ms plain, final spins identical).  The counters left are the
+    graph run's."""
+    n = sco.n_chains
+    start = [sco.spins(c) for c in range(n)]
+    ms_plain = time_steps(sco, first, steps, torch, graph=False)
+    after_plain = [sco.spins(c) for c in range(n)]
+    for c in range(n):
+        sco.set_spins(c, start[c])
+    sco.reset_counters()
+    ms_graph = time_steps(sco, first, steps, torch, graph=True)
+    same = all(np.array_equal(sco.spins(c), after_plain[c]) for c in range(n))
+    return ms_graph, ms_plain, same
+
+
 def host_cpu():
     """The host's logical CPUs and CPU model (for the oracle's timing)."""
     model = "unknown"
@@ -214,12 +230,14 @@ def workload_leg(name, params, steps, torch, SCO, ChainParams, autotune=True):
     sco = SCO([ChainParams(**p) for p in params], device="cuda:0")
     sched = sco.autotune(2) if autotune else None
     sco.run(0, 2)
-    ms = time_steps(sco, 2, steps, torch)
-    ms_plain = time_steps(sco, 2 + steps, steps, torch, graph=False)
+    import numpy as np
+
+    ms, ms_plain, same = time_both(sco, 2, steps, torch, np)
     obs = sco.observables()
     spins = sum(p["L"] ** 2 for p in params)
     attempts = sum(p["L"] ** 2 * p["n_sw"] for p in params)
     out = {"chains": len(params), "spins": spins, "steps": steps, "ms_per_step": ms, "ms_per_step_plain": ms_plain,
+           "graph_equals_plain": same,
            "attempts_per_s": attempts / (ms / 1e3), "schedule": sched,
            "rechecks": int(sum(o["rechecks"] for o in obs)),
            "attempts_total": int(sum(o["attempts"] for o in obs))}
@@ -268,13 +286,13 @@ def main() -> int:
     progress(f"warmup {args.warmup} steps done")
 
     first = args.warmup
-    ms_per_step = time_steps(sco, first, args.steps, torch)
+    # the timed steps as plain launches, then the same steps from the same spins as
+    # one HIP-graph replay; `value` is the graph replay's
+    ms_per_step, ms_plain, graph_same = time_both(sco, first, args.steps, torch, np)
     value = N * p["n_sw"] / (ms_per_step / 1e3)
     obs = sco.observables()[0]
-    progress(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} attempts/s")
-    # the same steps as plain launches, for comparison (the chain moves on: later steps)
-    ms_plain = time_steps(sco, 1000 + first, args.steps, torch, graph=False)
-    progress(f"plain launches: {ms_plain:.3f} ms/step")
+    progress(f"timed {args.steps} steps: graph {ms_per_step:.3f} ms/step ({value:.4g} attempts/s), "
+             f"plain launches {ms_plain:.3f} ms/step, same spins {graph_same}")
 
     # one traced step: block 0's phase marks inside the persistent kernel
     sco.trace(True)
@@ -367,6 +385,7 @@ def main() -> int:
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "ms_per_step_plain_launches": ms_plain,
+        "graph_equals_plain_launches": graph_same,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

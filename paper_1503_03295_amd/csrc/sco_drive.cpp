@@ -7,6 +7,8 @@
 //   sco_drive L periodic T kappa n_sw warmup steps split
 #include <hip/hip_runtime.h>
 
+#include <link.h>
+
 #include <cstdio>
 #include <cstdlib>
 
@@ -20,6 +22,22 @@
 static int die(const char* what, int rc) {
   std::fprintf(stderr, "sco_drive: %s failed: %s (%d)\n", what, sco_strerror(rc), rc);
   return 1;
+}
+
+// The address range of every loaded library, on stderr: a fault reported at exit
+// (by a profiler's handler, as raw addresses) can then be put down to a library.
+static int print_range(dl_phdr_info* info, size_t, void*) {
+  uintptr_t lo = UINTPTR_MAX, hi = 0;
+  for (int i = 0; i < info->dlpi_phnum; ++i) {
+    const ElfW(Phdr)& ph = info->dlpi_phdr[i];
+    if (ph.p_type != PT_LOAD) continue;
+    const uintptr_t b = info->dlpi_addr + ph.p_vaddr;
+    if (b < lo) lo = b;
+    if (b + ph.p_memsz > hi) hi = b + ph.p_memsz;
+  }
+  if (hi > lo) std::fprintf(stderr, "library %#zx-%#zx %s\n", static_cast<size_t>(lo), static_cast<size_t>(hi),
+                            info->dlpi_name[0] ? info->dlpi_name : "(main)");
+  return 0;
 }
 
 int main(int argc, char** argv) {
@@ -107,5 +125,8 @@ int main(int argc, char** argv) {
   HIP_OK(hipEventDestroy(e1));
   HIP_OK(hipStreamDestroy(s));
   HIP_OK(hipFree(ws));
+  std::fflush(stdout);
+  dl_iterate_phdr(print_range, nullptr);
+  std::fflush(stderr);
   return 0;
 }
