@@ -44,6 +44,101 @@ bool valid(const sco_chain_params& p) {
 // V^max = 2 D / r^3 of the dipolar tensor for Heisenberg spins
 double table_d(const sco_chain_params& p) { return p.model == SCO_MODEL_HEIS ? 2.0 * p.D : p.D; }
 
+// ---- exact transform plans for the pair correlations (Ising chains)
+bool is_prime32(uint32_t x) {
+  if (x < 2) return false;
+  for (uint32_t i = 2; static_cast<uint64_t>(i) * i <= x; ++i)
+    if (x % i == 0) return false;
+  return true;
+}
+uint32_t pow_mod(uint64_t b, uint64_t e, uint32_t p) {
+  uint64_t r = 1;
+  b %= p;
+  for (; e; e >>= 1, b = b * b % p)
+    if (e & 1) r = r * b % p;
+  return static_cast<uint32_t>(r);
+}
+// radices 8, 4, 2, 3, 5, 7 of n (powers of two by 8s, then one 4 or 2); false when n has
+// another prime factor
+bool ntt_radices(int n, NttPlan& pl) {
+  pl.nrad = 0;
+  int twos = 0;
+  while (n % 2 == 0) {
+    n /= 2;
+    ++twos;
+  }
+  for (; twos >= 3; twos -= 3) pl.rad[pl.nrad++] = 8;
+  if (twos > 0) pl.rad[pl.nrad++] = 1 << twos;
+  for (int r : {3, 5, 7})
+    while (n % r == 0) {
+      n /= r;
+      pl.rad[pl.nrad++] = r;
+      if (pl.nrad >= 24) return false;
+    }
+  return n == 1;
+}
+// The transform of one chain's lattice: length L (periodic) or the smallest 2^a 3^b
+// 5^c 7^d >= 2L - 1 (open, zero-padded so the cyclic correlation is the linear one);
+// n = 0 when L has another prime factor or no prime below 2^31 fits.
+NttPlan ntt_plan(const sco_chain_params& q) {
+  NttPlan pl{};
+  if (q.model != SCO_MODEL_ISING) return pl;
+  const int64_t L = q.L;
+  const uint64_t minp = 2 * static_cast<uint64_t>(L) * static_cast<uint64_t>(L) + 1;  // |C| <= L^2
+  if (minp >= (1ull << 30)) return pl;
+  int n = 0;
+  if (q.periodic) {
+    n = static_cast<int>(L);
+    if (!ntt_radices(n, pl)) return NttPlan{};
+  } else {
+    for (n = static_cast<int>(2 * L - 1); n < 8 * L; ++n)
+      if (ntt_radices(n, pl)) break;
+  }
+  if (n < 2 || n > 16384) return NttPlan{};
+  uint32_t p = 0;
+  for (uint64_t k = ((1ull << 31) - 1) / static_cast<uint64_t>(n); k > 0; --k) {
+    const uint64_t c = k * static_cast<uint64_t>(n) + 1;
+    if (c <= minp) break;
+    if (c < (1ull << 31) && is_prime32(static_cast<uint32_t>(c))) {
+      p = static_cast<uint32_t>(c);
+      break;
+    }
+  }
+  if (p == 0) return NttPlan{};
+  pl.n = n;
+  pl.p = p;
+  uint32_t inv = p;  // p^-1 mod 2^32 by Newton's iteration (p odd)
+  for (int i = 0; i < 5; ++i) inv *= 2u - p * inv;
+  pl.pinv = 0u - inv;
+  pl.one = static_cast<uint32_t>((1ull << 32) % p);
+  const uint32_t ninv = pow_mod(static_cast<uint64_t>(n), p - 2, p);
+  pl.ninv2 = static_cast<uint32_t>(static_cast<uint64_t>(ninv) * ninv % p);
+  return pl;
+}
+// w^e in Montgomery form, e < n, w a primitive n-th root of unity mod p
+std::vector<uint32_t> ntt_twiddles(const NttPlan& pl) {
+  const uint32_t p = pl.p;
+  std::vector<uint32_t> f;  // the prime factors of p - 1
+  uint32_t x = p - 1;
+  for (uint32_t i = 2; static_cast<uint64_t>(i) * i <= x; ++i)
+    if (x % i == 0) {
+      f.push_back(i);
+      while (x % i == 0) x /= i;
+    }
+  if (x > 1) f.push_back(x);
+  uint32_t g = 2;
+  for (;; ++g) {
+    bool prim = true;
+    for (uint32_t q : f) prim = prim && pow_mod(g, (p - 1) / q, p) != 1;
+    if (prim) break;
+  }
+  const uint32_t w = pow_mod(g, (p - 1) / static_cast<uint32_t>(pl.n), p);
+  std::vector<uint32_t> tw(pl.n);
+  uint64_t we = 1;
+  for (int e = 0; e < pl.n; ++e, we = we * w % p) tw[e] = static_cast<uint32_t>((we << 32) % p);
+  return tw;
+}
+
 using TableKey = std::tuple<int, int, int, double>;  // L, periodic, n_images, D
 
 struct Layout {
@@ -62,6 +157,7 @@ struct Layout {
   size_t off_spin_bak = 0, off_st_bak = 0;
   size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   size_t off_acc = 0, off_spin3 = 0, off_hpart = 0, off_hres = 0, off_csz = 0;
+  size_t off_ntt = 0, off_tw = 0;  // transform buffers (2 n^2) and twiddles (n) of the largest plan
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -156,6 +252,10 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   lay.off_hpart = take(sizeof(double) * 2 * (maxN / 256 + 2));
   lay.off_hres = take(sizeof(double) * 2);
   lay.off_csz = take(sizeof(unsigned long long) * 256);
+  int64_t nmax = 0;
+  for (int c = 0; c < n; ++c) nmax = std::max<int64_t>(nmax, ntt_plan(p[c]).n);
+  lay.off_ntt = take(sizeof(uint32_t) * 2 * nmax * nmax);
+  lay.off_tw = take(sizeof(uint32_t) * nmax);
   lay.bytes = off;
   return SCO_OK;
 }
@@ -1198,9 +1298,17 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
       HIP_TRY(hipStreamSynchronize(c->stream));
       continue;
     }
+    const NttPlan plan = ntt_plan(c->params[ci]);
+    if (plan.n > 0) {
+      const std::vector<uint32_t> tw = ntt_twiddles(plan);
+      HIP_TRY(hipMemcpyAsync(at<uint32_t>(c, L.off_tw), tw.data(), sizeof(uint32_t) * tw.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    }
     HIP_TRY(sco_dev::obs_dipolar(c->stream, d.hd, d.J, d.K, d.L, d.periodic, at<int8_t>(c, L.off_spin), d.vbase,
                                  at<uint32_t>(c, L.off_bits), at<double>(c, L.off_prod), at<double>(c, L.off_dpart),
-                                 at<double>(c, L.off_dres) + ci));
+                                 at<double>(c, L.off_dres) + ci, &plan, at<uint32_t>(c, L.off_ntt),
+                                 at<uint32_t>(c, L.off_tw)));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the twiddles of the next chain overwrite these
   }
   std::vector<ChainState> st(c->n);
   std::vector<unsigned long long> sums(2 * c->n);

@@ -131,6 +131,17 @@ struct StepArgs {
 enum : uint32_t { PH_SWITCH = 1u, PH_COLOR = 2u, PH_SWEEP = 4u };
 
 // Host-side launchers of the kernels (defined next to the kernels).
+// An exact transform of one lattice's spins for the pair correlations (host-chosen).
+struct NttPlan {
+  int32_t n;        // transform length per dimension (0: no plan, the direct kernels run)
+  int32_t nrad;     // radices of the Stockham passes, in order
+  int32_t rad[24];
+  uint32_t p;       // prime, n | p - 1, 2 L^2 + 1 < p < 2^31
+  uint32_t pinv;    // -p^-1 mod 2^32
+  uint32_t one;     // 2^32 mod p (1 in Montgomery form)
+  uint32_t ninv2;   // n^-2 mod p
+};
+
 namespace sco_dev {
 hipError_t table_j(hipStream_t s, const uint32_t* hd, int K, int L, int periodic, int n_images,
                    double D, double* J);
@@ -156,9 +167,11 @@ hipError_t bond_hist(hipStream_t s, const int32_t* row_ptr, const int32_t* col, 
                      int N, unsigned long long* counts);
 // acc[c] += this step's |M|, M^2, directed bonds and maximum degrees
 hipError_t anneal_acc(hipStream_t s, const ChainState* st, AnnealAcc* acc, int n);
+
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L,
                        int periodic, const int8_t* spin, int64_t vbase, uint32_t* bits,
-                       double* prod, double* part, double* out);
+                       double* prod, double* part, double* out, const NttPlan* plan, uint32_t* nbuf,
+                       uint32_t* tw);
 // Device address of the current GPU's copy of the static scratch array
 // (SCO_NOALLOC_BYTES, 256-byte aligned).
 hipError_t noalloc_scratch(void** ptr);

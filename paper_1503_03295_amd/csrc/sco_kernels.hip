@@ -3261,6 +3261,109 @@ extern "C" __global__ void k_obs_corr_bits(const uint32_t* __restrict__ hd, cons
   prod[m] = J[m] * static_cast<double>(cm);
 }
 
+// ------------------------------------------------ pair correlations by an exact transform
+// The same owned-pair correlations C_m from a number-theoretic transform of the spins:
+// arithmetic modulo a prime p < 2^31 with n | p - 1 (chosen on the host, with a
+// primitive n-th root of unity w), values in Montgomery form (R = 2^32).  The 2-D
+// transform S(k) of the spins on an n x n array (the lattice, zero-padded to
+// n >= 2L - 1 when it is open), the product S(k) S(-k), and the inverse transform
+// give n^2 C(d), C(d) = sum_x s(x) s(x + d) cyclic over n, exactly as integers mod p
+// (|C| < p / 2).  Every 1-D transform runs as Stockham passes of radix 2..8 along the
+// rows, then along the columns.
+
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
+  const uint64_t t = static_cast<uint64_t>(a) * b;  // < p^2 < 2^62
+  const uint32_t m = static_cast<uint32_t>(t) * pinv;
+  const uint64_t u = (t + static_cast<uint64_t>(m) * p) >> 32;  // < 2 p
+  return u >= p ? static_cast<uint32_t>(u - p) : static_cast<uint32_t>(u);
+}
+__device__ __forceinline__ uint32_t mod_add(uint32_t a, uint32_t b, uint32_t p) {
+  const uint32_t s = a + b;  // < 2^32 for a, b < p < 2^31
+  return s >= p ? s - p : s;
+}
+
+// spins (one chain, row-major L x L) into the n x n array: R mod p for +1, p - (R mod
+// p) for -1, 0 in the padding
+extern "C" __global__ void k_ntt_load(const int8_t* __restrict__ spin, int64_t vbase, int L, int n,
+                                      uint32_t one, uint32_t p, uint32_t* __restrict__ out) {
+  const int64_t t = gtid();
+  if (t >= static_cast<int64_t>(n) * n) return;
+  const int y = static_cast<int>(t / n), x = static_cast<int>(t - static_cast<int64_t>(y) * n);
+  uint32_t v = 0;
+  if (x < L && y < L) v = spin[vbase + static_cast<int64_t>(y) * L + x] > 0 ? one : p - one;
+  out[t] = v;
+}
+
+// One Stockham pass of radix R over every row (dim 0) or column (dim 1): the pass
+// joins R transforms of length Ns into transforms of length Ns R; tw[e] = w^e
+// (Montgomery form), e < n; inv: the inverse transform (w^-1), unscaled.
+template <int R>
+__global__ void k_ntt_pass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int n, int Ns, int dim,
+                           const uint32_t* __restrict__ tw, uint32_t p, uint32_t pinv, int inv) {
+  const int64_t t = gtid();
+  const int m = n / R;
+  if (t >= static_cast<int64_t>(n) * m) return;
+  int line, j;
+  if (dim == 0) {  // consecutive threads along a row
+    line = static_cast<int>(t / m);
+    j = static_cast<int>(t - static_cast<int64_t>(line) * m);
+  } else {  // consecutive threads across the columns
+    j = static_cast<int>(t / n);
+    line = static_cast<int>(t - static_cast<int64_t>(j) * n);
+  }
+  auto at = [&](int x) -> int64_t {
+    return dim == 0 ? static_cast<int64_t>(line) * n + x : static_cast<int64_t>(x) * n + line;
+  };
+  const int k = j % Ns;
+  const int step = n / (Ns * R);  // the pass's twiddles are w_{Ns R}^{k q} = w^{step k q}, step k q < n
+  uint32_t a[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const uint32_t v = in[at(j + q * m)];
+    const int e = step * k * q;
+    a[q] = q == 0 ? v : mont_mul(v, tw[inv && e ? n - e : e], p, pinv);
+  }
+  const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    uint32_t acc = a[0];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      const int e = static_cast<int>((static_cast<int64_t>(m) * q * u) % n);  // w_R^{q u}
+      acc = mod_add(acc, mont_mul(a[q], tw[inv && e ? n - e : e], p, pinv), p);
+    }
+    out[at(base + u * Ns)] = acc;
+  }
+}
+
+// S(k) S(-k) of the forward transform
+extern "C" __global__ void k_ntt_square(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int n,
+                                        uint32_t p, uint32_t pinv) {
+  const int64_t t = gtid();
+  if (t >= static_cast<int64_t>(n) * n) return;
+  const int ky = static_cast<int>(t / n), kx = static_cast<int>(t - static_cast<int64_t>(ky) * n);
+  const int64_t tm = static_cast<int64_t>(ky ? n - ky : 0) * n + (kx ? n - kx : 0);
+  out[t] = mont_mul(in[t], in[tm], p, pinv);
+}
+
+// prod[m] = J_m C_m from the inverse transform (n^2 C(d) in Montgomery form, times
+// n^-2 mod p): the owned pairs of displacement d_m are C(d_m), halved for the
+// self-conjugate displacements of a periodic lattice, whose pairs C counts twice
+extern "C" __global__ void k_ntt_gather(const uint32_t* __restrict__ cn, int n, int L, int periodic,
+                                        const uint32_t* __restrict__ hd, const double* __restrict__ J, int K,
+                                        uint32_t ninv2, uint32_t p, uint32_t pinv, double* __restrict__ prod) {
+  const int64_t m = gtid();
+  if (m >= K) return;
+  const uint32_t hp = hd[m];
+  const int dx = static_cast<int16_t>(hp & 0xFFFFu), dy = static_cast<int16_t>(hp >> 16);
+  const int ix = dx < 0 ? dx + n : dx, iy = dy < 0 ? dy + n : dy;
+  const uint32_t v = mont_mul(cn[static_cast<int64_t>(iy) * n + ix], ninv2, p, pinv);
+  long long c = v > (p >> 1) ? static_cast<long long>(v) - static_cast<long long>(p) : static_cast<long long>(v);
+  const int h = L >> 1;
+  if (periodic && ((dy == 0 && dx == h) || (dy == h && (dx == 0 || dx == h)))) c /= 2;
+  prod[m] = J[m] * static_cast<double>(c);
+}
+
 // Same quantity for any L, pair by pair (small lattices).
 extern "C" __global__ void k_obs_corr_plain(const uint32_t* __restrict__ hd, const double* __restrict__ J,
                                             int K, int L, int periodic, const int8_t* __restrict__ spin,
@@ -3439,8 +3542,46 @@ hipError_t anneal_acc(hipStream_t s, const ChainState* st, AnnealAcc* acc, int n
 
 hipError_t obs_dipolar(hipStream_t s, const uint32_t* hd, const double* J, int K, int L, int periodic,
                        const int8_t* spin, int64_t vbase, uint32_t* bits, double* prod, double* part,
-                       double* out) {
-  if (L % 32 == 0) {
+                       double* out, const NttPlan* plan, uint32_t* nbuf, uint32_t* tw) {
+  if (plan && plan->n > 0) {
+    const int n = plan->n;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    const dim3 g1(static_cast<uint32_t>((nn + 255) / 256));
+    uint32_t* A = nbuf;
+    uint32_t* B = nbuf + nn;
+    hipLaunchKernelGGL(k_ntt_load, g1, dim3(256), 0, s, spin, vbase, L, n, plan->one, plan->p, A);
+    auto passes = [&](int inv) {
+      for (int dim = 0; dim < 2; ++dim) {
+        int Ns = 1;
+        for (int i = 0; i < plan->nrad; ++i) {
+          const int r = plan->rad[i];
+          const dim3 g(static_cast<uint32_t>((nn / r + 255) / 256));
+          switch (r) {
+            case 2: hipLaunchKernelGGL(k_ntt_pass<2>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+            case 3: hipLaunchKernelGGL(k_ntt_pass<3>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+            case 4: hipLaunchKernelGGL(k_ntt_pass<4>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+            case 5: hipLaunchKernelGGL(k_ntt_pass<5>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+            case 7: hipLaunchKernelGGL(k_ntt_pass<7>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+            default: hipLaunchKernelGGL(k_ntt_pass<8>, g, dim3(256), 0, s, A, B, n, Ns, dim, tw, plan->p, plan->pinv, inv); break;
+          }
+          Ns *= r;
+          uint32_t* x = A;
+          A = B;
+          B = x;
+        }
+      }
+    };
+    passes(0);
+    hipLaunchKernelGGL(k_ntt_square, g1, dim3(256), 0, s, A, B, n, plan->p, plan->pinv);
+    {
+      uint32_t* x = A;
+      A = B;
+      B = x;
+    }
+    passes(1);
+    hipLaunchKernelGGL(k_ntt_gather, dim3((K + 255) / 256), dim3(256), 0, s, A, n, L, periodic, hd, J, K,
+                       plan->ninv2, plan->p, plan->pinv, prod);
+  } else if (L % 32 == 0) {
     const int W = L / 32;
     hipLaunchKernelGGL(k_obs_pack, dim3((L * W + 255) / 256), dim3(256), 0, s, spin, vbase, L, W, bits);
     hipLaunchKernelGGL(k_obs_corr_bits, dim3((K + 255) / 256), dim3(256), 0, s, hd, J, K, L, periodic, bits,
