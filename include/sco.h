@@ -251,9 +251,12 @@ int sco_get_flags(sco_ctx* ctx, int64_t* last, int64_t* seen);
 
 /* Observables of every chain into host_out[n_chains]; synchronises.  E_exchange and M
  * follow Eq. (6) restricted to perpendicular spins; E_dipolar = sum_m J_m C_m with the
- * exact integer pair correlation C_m of each half-displacement (O(N K / 32) bit
- * operations); n_edges, delta_union, q and the colours are the graph statistics of
- * Sec. 3.2 (mean degree 2 n_edges / N) for the last switching and colouring. */
+ * exact integer pair correlation C_m of each half-displacement, from a number-theoretic
+ * transform of the spins (O(N log N); lattice sizes with a prime factor above 7 take a
+ * direct O(N K / 32) count); Heisenberg chains: E_exchange, E_dipolar (the full tensor
+ * of Eq. 6, O(N K)) and m_phi of Eq. (7).  n_edges, delta_union, q and the colours are
+ * the graph statistics of Sec. 3.2 (mean degree 2 n_edges / N) for the last switching
+ * and colouring. */
 int sco_observables(sco_ctx* ctx, sco_obs* host_out);
 
 /* The same without the dipolar energy (E and E_dipolar are NaN): integer observables,

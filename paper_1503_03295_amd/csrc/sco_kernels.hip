@@ -1,19 +1,24 @@
 // sco_kernels.hip -- gfx950 kernels of the stochastic-cutoff (SCO) step.
 //
 // One SCO step (Endo, Toga & Sasaki, Sec. 2.1-2.3, Fig. 1) runs as one persistent
-// kernel k_step<phases> whose blocks are all resident (cooperative launch, one
-// 1024-thread block per CU):
+// kernel k_step<phases, model> whose blocks are all resident (cooperative launch, one
+// 1024-thread block per CU); model selects Ising spins or the Heisenberg spins of
+// Eq. (6):
 //   step (1)  phase_switch    switch every dipolar bond (Eqs. 1-3): geometric skipping
 //                             over the cumulative coupling, then thinning; survivors
 //                             appended with one atomic per wavefront (ballot count)
-//             scan_lookback   single-pass prefix sum of the degrees (row offsets)
+//             scan_two_pass   prefix sum of the degrees (row offsets): tile sums, one
+//                             device barrier, then every tile scanned in LDS
 //             phase_scatter   both directions of every survivor into the CSR
 //             phase_rowsort   rows ascending by neighbour, union degree, Delta
 //   step (2)  phase_kw_local  Kuhn-Wattenhofer levels whose groups fit in one LDS tile
 //             phase_kw_global the remaining levels, colour class by colour class
+//             (phase_color_bcr: whole-graph colour reduction, a colouring variant)
 //   step (3)  phase_sweep     Metropolis on H' (Eq. 4), one colour class at a time
+//             (phase_sweep_heis for Heisenberg spins)
 // Device-wide barriers separate dependent phases; every wait in them is bounded and a
 // wait that runs out raises SCO_FLAG_TIMEOUT, after which every wave leaves the kernel.
+// The observables (energies, M_phi, graph statistics) are separate kernels.
 //
 // Floating point: FP64 with contraction disabled (-ffp-contract=off); every decision
 // that the CPU reference also takes is evaluated with the same operations in the
