@@ -1543,7 +1543,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
   __shared__ int32_t t_off[SCO_MAXQ + 1];
   __shared__ int32_t t_fill[SCO_MAXQ];
   __shared__ int32_t t_wsum[kWaves];
-  __shared__ int32_t t_rounds, t_nbonded, t_pos;
+  __shared__ int32_t t_rounds, t_nbonded;
   const uint32_t lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int tid = static_cast<int>(threadIdx.x);
@@ -1686,7 +1686,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       const uint32_t mH = magic16(static_cast<uint32_t>(H));
       const int npend = static_cast<int>(pending_count(n, H));
       for (int k = threadIdx.x; k <= q; k += kBlock) t_off[k] = 0;
-      if (threadIdx.x == 0) t_rounds = t_pos = 0;
+      if (threadIdx.x == 0) t_rounds = 0;
       __syncthreads();
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
@@ -1726,122 +1726,92 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       }
       __syncthreads();
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 80 + p);
-      // The classes run from the top down with no barrier between them: a site
-      // decides as soon as its same-group pending neighbours of higher classes have
-      // (their LDS words carry a round), re-reading the words while it waits; lower
-      // classes are ignored and wait for it.  List positions are dealt to the lanes
-      // from a block counter in increasing order (top class first); a lane holds one
-      // site at a time, so a waiting lane holds up neither its wave nor the block, and
-      // every wait is on an earlier position of a higher class and, by induction over
-      // the classes, ends.
+      // The classes run from the top down, a block barrier after each: when a class
+      // runs, every pending same-group neighbour of a higher class has decided (its
+      // word carries a round) and those of lower classes have not, so no site waits.
+      // Most pending sites sit in the two lowest classes (rule (2)' leaves most sites
+      // of a lattice with colours 0 and 1), which are throughput-bound: the visit is
+      // kept short and free of branches on the neighbours, and each thread takes two
+      // sites of a class at a time, their LDS reads in flight together.
       auto run_classes = [&](auto set_tag) {
         using Set = decltype(set_tag);
-        // the words are read and written with workgroup-scope atomics: every wait sees
-        // the other waves' decisions, and the accesses stay LDS instructions
-        auto cr_ld = [&](int k) -> int { return __hip_atomic_load(&t_cr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+        const int NL = L * L;
+        const int gsz2 = 2 * H;
         int tmax = 0;
-        int cls = q - 1;  // class of the lane's current position (only decreases)
-        bool have = false, more = true;
-        int i = 0, cl = 0;
-        int glo = 0, gmid = 0, ghi = 0;  // the site's group at this level: [glo, ghi), pending from gmid
-        int jt[4] = {-1, -1, -1, -1};
-        int e0 = 0, e1 = 0, g0 = 0, g1 = 0;  // in-tile bonds in LDS, or the row in memory
-        for (uint32_t spin = 0;; ++spin) {
-          // lanes without a site take the next positions: one LDS atomic per wave
-          const bool need = !have && more;
-          const uint64_t nm = __ballot(need);
-          if (nm != 0) {
-            const int leader = __ffsll(static_cast<unsigned long long>(nm)) - 1;
-            int base = 0;
-            if (static_cast<int>(lane) == leader) base = atomicAdd(&t_pos, __popcll(nm));
-            base = __shfl(base, leader);
-            if (need) {
-              const int j = base + __popcll(nm & ((1ull << lane) - 1ull));
-              if (j >= npend) {
-                more = false;
-              } else {
-                const int kx = npend - 1 - j;
-                while (kx < t_off[cls]) --cls;
-                cl = cls;
-                i = t_list[kx];
-                glo = static_cast<int>(__umul24(div16(i, mq) >> p, 2 * H));
-                gmid = glo + H;
-                ghi = min(glo + 2 * H, n);
-                const int t = x0 + i, dy = div16(t, mL);
-                int nb[4];
-                nn_sites(t - dy * L, y0 + dy, L, periodic, nb);
-                // the checkerboard product colours the bonds alone
+        // the decision of the site at list position kx
+        auto decide = [&](int kx) {
+          const int i = t_list[kx];
+          const int glo = static_cast<int>(__umul24(div16(i, mq) >> p, gsz2));
+          const int gmid = glo + H;
+          const uint32_t gsz = static_cast<uint32_t>(min(glo + gsz2, n) - glo);
+          const int t = x0 + i, dy = div16(t, mL);
+          const int x = t - dy * L, y = y0 + dy;
+          // tile indices of the lattice neighbours (+x, -x, +y, -y); -1 for none (open
+          // lattice ends; the checkerboard product colours the bonds alone)
+          int jn[4];
+          jn[0] = x + 1 < L ? i + 1 : (periodic ? i + 1 - L : -1);
+          jn[1] = x > 0 ? i - 1 : (periodic ? i - 1 + L : -1);
+          jn[2] = y + 1 < L ? i + L : (periodic ? i + L - NL : -1);
+          jn[3] = y > 0 ? i - L : (periodic ? i - L + NL : -1);
+          Set taken;
+          int rmax = 0;
+          // a neighbour counts when in the group and not pending, or pending and
+          // decided at this level (its colour then is the new one)
+          auto visit = [&](int j, int w) {
+            const bool same = static_cast<uint32_t>(j - glo) < gsz;
+            const bool pend = j >= gmid;
+            const int rj = w >> 8;
+            const bool on = same && (!pend || rj != 0);
+            rmax = max(rmax, on && pend ? rj : 0);
+            taken.add_if(on, w & 0xFF);
+          };
+          int w[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) jt[u] = nb[u] >= 0 && !checker ? nb[u] - v0 : -1;
-                e0 = e1 = g0 = g1 = 0;
-                const uint32_t mw = t_bmask[i >> 5];
-                if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
-                  const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
-                  const int eb = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
-                  if (eb <= kAdjCap) {
-                    e0 = t_boff[r];
-                    e1 = eb;
-                  } else {
-                    g0 = a.row_ptr[gt0 + i];
-                    g1 = a.row_ptr[gt0 + i + 1];
-                    row_checked(a, g0, g1);
-                  }
-                }
-                have = true;
+          for (int u = 0; u < 4; ++u) {
+            if (checker) jn[u] = -1;
+            w[u] = t_cr[static_cast<uint32_t>(jn[u] - glo) < gsz ? jn[u] : i];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) visit(jn[u], w[u]);
+          const uint32_t mw = t_bmask[i >> 5];
+          if (P > 0 && ((mw >> (i & 31)) & 1u)) {  // the site has in-tile bonds
+            const int r = static_cast<int>(t_brank[i >> 5]) + __popc(mw & ((1u << (i & 31)) - 1u));
+            const int eb = r < kBondedCap ? t_boff[r + 1] : kAdjCap + 1;
+            if (eb <= kAdjCap) {
+              for (int e = t_boff[r]; e < eb; ++e) {
+                const int j = t_adj[e];  // 0xFFFF: a partner outside the tile
+                visit(j, t_cr[j < n ? j : i]);
+              }
+            } else {  // the row did not fit the LDS lists: read from global memory
+              int g0 = a.row_ptr[gt0 + i], g1 = a.row_ptr[gt0 + i + 1];
+              row_checked(a, g0, g1);
+              for (int e = g0; e < g1; ++e) {
+                const int j = a.col[e] - gt0;
+                visit(j, t_cr[j >= 0 && j < n ? j : i]);
               }
             }
           }
-          if (__ballot(have || more) == 0) break;
-          bool waiting = false;
-          if (have) {
-            Set taken;
-            int rmax = 0;
-            bool ready = true;
-            // neighbour j (tile index, -1 for none) with word w: same group only; a
-            // pending one counts once decided and one of a higher class must be
-            auto visit_w = [&](int jn, int w) {
-              // outside the tile (negative, or 0xFFFF from the adjacency) is another group
-              const bool same = jn >= glo && jn < ghi;
-              const bool pend = jn >= gmid;
-              const int rj = w >> 8;
-              const bool on = same && (!pend || rj != 0);
-              const int cj = w & 0xFF;
-              ready = ready && !(same && pend && rj == 0 && cj > cl && cj < q);
-              rmax = max(rmax, on && pend ? rj : 0);
-              taken.add_if(on, cj);
-            };
-            auto visit = [&](int jn) { visit_w(jn, cr_ld(jn >= 0 && jn < n ? jn : i)); };
-            // the four lattice neighbours' words are read back to back (the atomic
-            // loads keep their order, so each is issued before any is used)
-            int wt[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) wt[u] = cr_ld(jt[u] >= 0 && jt[u] < n ? jt[u] : i);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) visit_w(jt[u], wt[u]);
-            for (int e = e0; e < e1; ++e) visit(t_adj[e]);
-            for (int e = g0; e < g1; ++e) visit(a.col[e] - gt0);
-            if (ready) {
-              int nc = taken.first_free();
-              if (nc >= q) {
-                set_flag(a.sync, SCO_FLAG_PALETTE);
-                nc = q - 1;
-              }
-              __hip_atomic_store(&t_cr[i], static_cast<uint16_t>(nc | ((rmax + 1) << 8)), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-              tmax = max(tmax, rmax + 1);
-              have = false;
-            } else {
-              waiting = true;
+          int nc = taken.first_free();
+          if (nc >= q) {
+            set_flag(a.sync, SCO_FLAG_PALETTE);
+            nc = q - 1;
+          }
+          return static_cast<uint32_t>(nc | ((rmax + 1) << 8)) | (static_cast<uint32_t>(i) << 16);
+        };
+        for (int cl = q - 1; cl >= 0; --cl) {
+          const int k0 = t_off[cl], k1 = t_off[cl + 1];
+          for (int kx = k0 + tid; kx < k1; kx += 2 * kBlock) {
+            const uint32_t d0 = decide(kx);
+            const bool two = kx + kBlock < k1;
+            const uint32_t d1 = two ? decide(kx + kBlock) : 0u;
+            t_cr[d0 >> 16] = static_cast<uint16_t>(d0 & 0xFFFFu);
+            tmax = max(tmax, static_cast<int>((d0 >> 8) & 0xFFu));
+            if (two) {
+              t_cr[d1 >> 16] = static_cast<uint16_t>(d1 & 0xFFFFu);
+              tmax = max(tmax, static_cast<int>((d1 >> 8) & 0xFFu));
             }
           }
-          // pause only when no lane of the wave took new work
-          if (__ballot(waiting) != 0 && nm == 0) {
-            if (spin > kSpinLimit) {
-              set_flag(a.sync, SCO_FLAG_TIMEOUT);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
+          __syncthreads();
         }
         tmax = wave_max(tmax);
         if (lane == 0 && tmax > 0) atomicMax(&t_rounds, tmax);
