@@ -2,16 +2,17 @@
 """Throughput of the stochastic-cutoff (SCO) step on one MI355X.
 
 A step is one full pass of the method over the chain: switching of every dipolar
-bond + bond-graph assembly, Kuhn-Wattenhofer colouring + colour bucketing, and n_sw
-colour-ordered Metropolis sweeps, all in one persistent kernel launch (k_step<7u>).
-`value` = spin-update attempts per second over the timed steps (N * n_sw per step),
-the steps replayed as one HIP graph, inputs resident in HBM, HIP events on the
-library's stream.  `roofline` puts that kernel's algorithmic bytes per launch over
-its measured time against the HBM peak.  Extra legs: the three phases as separate
-launches, n_sw = 100, the 64-chain batch, the 9-chain mixed-precision workload (FP64
-vs FP32 + recheck), the annealing schedule, the colouring variants and the paper's
-Heisenberg model at L = 2304.  The CPU
-oracle is timed on a short sample of the same chain (one host thread).
+bond + bond-graph assembly (k_step<1u>), Kuhn-Wattenhofer colouring + colour
+bucketing (k_step<2u>), and n_sw colour-ordered Metropolis sweeps (k_step<4u>), three
+persistent cooperative launches.  `value` = spin-update attempts per second over the
+timed steps (N * n_sw per step), the steps replayed as one HIP graph, inputs resident
+in HBM, HIP events on the library's stream.  `roofline` puts the dominant kernel's
+algorithmic bytes per launch (the colouring's) over its mean launch duration on the
+same steps against the HBM peak; `roofline.step` does the same for the whole step.
+Extra legs: n_sw = 100, the 64-chain batch, the 9-chain mixed-precision workload
+(FP64 vs FP32 + recheck), the annealing schedule, the colouring variants and the
+paper's Heisenberg model at L = 2304.  The CPU oracle is timed on a short sample of
+the same chain (one host thread).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -83,7 +84,8 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_step<7u> launch from the committed rocprofv3 --pmc summary, or
+    """HBM bytes per launch of the dominant kernel (the colouring, k_step<2u>) from the
+    committed rocprofv3 --pmc summary, or
     None when the kernel sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_step_L2304_traffic.md")
     try:
@@ -111,12 +113,25 @@ def time_steps(sco, first, steps, torch, graph=True):
     return e0.elapsed_time(e1) / steps
 
 
-def time_both(sco, first, steps, torch, np):
+def time_both(sco, first, steps, torch, np, phases=False):
     """The same steps from the same spins as plain launches and as one HIP-graph
-    replay: (ms graph, ms plain, final spins identical).  The counters left are the
-    graph run's."""
+    replay: (ms graph, ms plain, final spins identical, per-phase ms).  With `phases`
+    the steps run a third time as the three phase launches one call at a time, each
+    timed by HIP events on the library's stream (the mean launch duration of each
+    phase kernel over the timed steps).  The counters left are the graph run's."""
     n = sco.n_chains
     start = [sco.spins(c) for c in range(n)]
+    phase_ms = None
+    if phases:
+        acc = np.zeros(3)
+        for t in range(first, first + steps):
+            sco.switch(t)
+            sco.color()
+            sco.sweep(t, max(p.n_sw for p in sco.params))
+            acc += np.array(sco.phase_times())
+        phase_ms = acc / steps
+        for c in range(n):
+            sco.set_spins(c, start[c])
     ms_plain = time_steps(sco, first, steps, torch, graph=False)
     after_plain = [sco.spins(c) for c in range(n)]
     for c in range(n):
@@ -124,7 +139,7 @@ def time_both(sco, first, steps, torch, np):
     sco.reset_counters()
     ms_graph = time_steps(sco, first, steps, torch, graph=True)
     same = all(np.array_equal(sco.spins(c), after_plain[c]) for c in range(n))
-    return ms_graph, ms_plain, same
+    return ms_graph, ms_plain, same, phase_ms
 
 
 def host_cpu():
@@ -232,7 +247,7 @@ def workload_leg(name, params, steps, torch, SCO, ChainParams, autotune=True):
     sco.run(0, 2)
     import numpy as np
 
-    ms, ms_plain, same = time_both(sco, 2, steps, torch, np)
+    ms, ms_plain, same, _ = time_both(sco, 2, steps, torch, np)
     obs = sco.observables()
     spins = sum(p["L"] ** 2 for p in params)
     attempts = sum(p["L"] ** 2 * p["n_sw"] for p in params)
@@ -288,7 +303,7 @@ def main() -> int:
     first = args.warmup
     # the timed steps as plain launches, then the same steps from the same spins as
     # one HIP-graph replay; `value` is the graph replay's
-    ms_per_step, ms_plain, graph_same = time_both(sco, first, args.steps, torch, np)
+    ms_per_step, ms_plain, graph_same, timed_phase_ms = time_both(sco, first, args.steps, torch, np, phases=True)
     value = N * p["n_sw"] / (ms_per_step / 1e3)
     obs = sco.observables()[0]
     progress(f"timed {args.steps} steps: graph {ms_per_step:.3f} ms/step ({value:.4g} attempts/s), "
@@ -325,7 +340,9 @@ def main() -> int:
     pb = phase_bytes(N, E, c, M, P, k_mean, p["kappa"] == 1.0, p["n_sw"], accept)
     names = ["switch", "color", "sweep"]
     step_bytes = sum(pb.values())
-    achieved = step_bytes / (ms_per_step / 1e3) / 1e9
+    # the dominant kernel of the step: the colouring launch, its algorithmic bytes over
+    # its mean launch duration on the timed steps
+    achieved = pb["color"] / (timed_phase_ms[1] / 1e3) / 1e9
     progress("phase ms: " + ", ".join(f"{n}={t:.3f}" for n, t in zip(names, phase_ms)))
 
     extra = {}
@@ -401,8 +418,12 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-            "kernel": "k_step<7u>", "algorithmic_bytes_per_launch": step_bytes,
+            "kernel": "k_step<2u, 0>", "algorithmic_bytes_per_launch": pb["color"],
+            "launch_ms": float(timed_phase_ms[1]),
+            "timed_phase_ms": dict(zip(names, [float(x) for x in timed_phase_ms])),
             "phase_bytes": pb,
+            "step": {"algorithmic_bytes": step_bytes, "achieved": step_bytes / (ms_per_step / 1e3) / 1e9,
+                     "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         },
         "cpu_baseline": cpu,
         "schedule": sched,

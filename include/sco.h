@@ -162,6 +162,14 @@ int sco_step(sco_ctx* ctx, uint64_t step);
  * before the failed step). */
 int sco_run(sco_ctx* ctx, uint64_t first_step, int n_steps);
 
+/* How sco_step, sco_run and sco_run_graph launch a step (Sec. 2.1 steps (A)-(C)):
+ * 0 (the default) the switching, colouring and sweep kernels one after another,
+ * 1 one launch of the fused kernel.  Same results; the three launches are faster
+ * (each phase kernel holds only its own registers, and the launch boundaries replace
+ * two device-wide barriers), and sco_phase_times then times the last step's phases.
+ * SCO_EINVAL for other values. */
+int sco_set_step_form(sco_ctx* ctx, int fused);
+
 /* For callers that cannot allocate device memory (code under stream capture, tight
  * serving loops, harnesses that forbid allocation): sco_init + sco_run + sco_get_spins
  * (+ sco_observables) of n_chains chains in one call that allocates nothing.  Their
@@ -285,7 +293,8 @@ int sco_get_graph(sco_ctx* ctx, int chain, int32_t* row_ptr, int32_t* col, int32
 int sco_get_tables(sco_ctx* ctx, int chain, int32_t* K, int32_t* dx, int32_t* dy, double* J,
                    double* C, double* theta, double* delta);
 
-/* Device time of the phases of the last sco_step/sco_run call, in ms:
+/* Device time of the phases, in ms: of the last sco_switch, sco_color and sco_sweep
+ * calls, or of the last step of sco_step / sco_run in the three-launch form.
  * out[0] switching + assembly, out[1] colouring, out[2] sweeps (events on the stream). */
 int sco_phase_times(sco_ctx* ctx, float* out3);
 

@@ -18,7 +18,7 @@ EXPORTS = [
     "sco_strerror", "sco_set_schedule", "sco_get_schedule", "sco_autotune", "sco_get_flags",
     "sco_counters", "sco_run_noalloc", "sco_run_graph", "sco_set_temperature", "sco_anneal",
     "sco_set_coloring", "sco_get_spins3", "sco_set_spins3", "sco_class_sizes", "sco_bond_histogram",
-    "sco_survival_by_distance", "sco_set_round_cap", "sco_set_fenced_sweeps", "sco_validate",
+    "sco_survival_by_distance", "sco_set_round_cap", "sco_set_fenced_sweeps", "sco_set_step_form", "sco_validate",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
         "sco_survival_by_distance": ([P, i32, P, P, i32, ctypes.POINTER(ctypes.c_int)], i32),
         "sco_set_round_cap": ([P, i32], i32),
         "sco_set_fenced_sweeps": ([P, i32], i32),
+        "sco_set_step_form": ([P, i32], i32),
         "sco_validate": ([P, i32, ctypes.POINTER(ctypes.c_int64)], i32),
         "sco_set_spins3": ([P, i32, P], i32),
         "sco_anneal": ([P, ctypes.POINTER(ctypes.c_double), i32, i32, i32, u64, ctypes.POINTER(StageC)], i32),

@@ -243,6 +243,11 @@ class SCO:
               "sco_survival_by_distance", self._h)
         return r[: n.value], p[: n.value]
 
+    def set_step_form(self, fused: bool) -> None:
+        """One fused launch per step (True) or the three phase launches (False, the
+        default); see sco_set_step_form."""
+        check(lib().sco_set_step_form(self._h, 1 if fused else 0), "sco_set_step_form", self._h)
+
     def set_fenced_sweeps(self, on: bool = True) -> None:
         """Full release/acquire barriers between the sweep's colour classes (see
         sco_set_fenced_sweeps); same results, slower."""

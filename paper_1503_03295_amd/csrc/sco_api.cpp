@@ -307,6 +307,7 @@ struct sco_ctx {
   int launched_blocks = 0;         // grid of the last launch (its barrier counters)
   int nsw_max = 0;
   int graph_state = 0;  // 0 no bond graph yet, 1 switched, 2 switched and coloured
+  int step_fused = 0;   // a step as one launch of the fused kernel (else three launches)
   bool trace_on = false;
   double wall_mhz = 100.0;
   unsigned long long* pinned = nullptr;            // read-back staging
@@ -369,7 +370,7 @@ int consume_flags(sco_ctx* c) {
 }
 
 // Launches `phases` for SCO step `step`.
-int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
+int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override, bool trace_reset = true) {
   if (step > 0xFFFFFFFFull) return SCO_EINVAL;
   if (c->blocks != c->launched_blocks) {
     // the barrier counters count arrivals in groups sized by the grid: start them
@@ -380,13 +381,39 @@ int launch(sco_ctx* c, uint32_t phases, uint64_t step, int nsw_override) {
   c->args.step = static_cast<uint32_t>(step);
   if (c->trace_on) {
     c->args.trace = at<unsigned long long>(c, c->lay.off_trace);
-    HIP_TRY(hipMemsetAsync(c->args.trace, 0, sizeof(unsigned long long), c->stream));
+    if (trace_reset) HIP_TRY(hipMemsetAsync(c->args.trace, 0, sizeof(unsigned long long), c->stream));
   } else {
     c->args.trace = nullptr;
   }
   c->args.nsw_override = nsw_override;
   c->args.nsw_max = nsw_override >= 0 ? nsw_override : c->nsw_max;
   HIP_TRY(sco_dev::step(c->stream, c->args, phases, c->blocks, c->model));
+  return SCO_OK;
+}
+
+// Full steps first_step .. first_step + n - 1: one launch of the fused kernel per step,
+// or (the default, measured faster: each phase kernel holds only its own registers,
+// and the launch boundaries replace two device-wide barriers) the switching,
+// colouring and sweep kernels one after another; the last step's phases are timed.
+int run_steps(sco_ctx* c, uint64_t first_step, int n) {
+  for (int s = 0; s < n; ++s) {
+    const uint64_t t = first_step + static_cast<uint64_t>(s);
+    const bool last = s + 1 == n && c->ev[0] != nullptr;  // (the allocation-free context has no events)
+    if (c->step_fused) {
+      const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, t, -1);
+      if (rc) return rc;
+    } else {
+      if (last) HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+      int rc = launch(c, PH_SWITCH, t, -1);
+      if (last && rc == SCO_OK) HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+      if (rc == SCO_OK) rc = launch(c, PH_COLOR, t, -1, false);
+      if (last && rc == SCO_OK) HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+      if (rc == SCO_OK) rc = launch(c, PH_SWEEP, t, -1, false);
+      if (last && rc == SCO_OK) HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+      if (rc) return rc;
+    }
+    c->graph_state = 2;
+  }
   return SCO_OK;
 }
 
@@ -751,21 +778,17 @@ int sco_sweep(sco_ctx* c, uint64_t step, int n_sw) {
 
 int sco_step(sco_ctx* c, uint64_t step) {
   if (!c) return SCO_EINVAL;
-  const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, step, -1);
-  if (rc == SCO_OK) c->graph_state = 2;
-  return rc;
+  return run_steps(c, step, 1);
 }
 
 int sco_run(sco_ctx* c, uint64_t first_step, int n_steps) {
   if (!c || n_steps < 0) return SCO_EINVAL;
-  for (int s = 0; s < n_steps; ++s) {
-    const int rc = launch(c, PH_SWITCH | PH_COLOR | PH_SWEEP, first_step + static_cast<uint64_t>(s), -1);
-    if (rc) return rc;
-    c->graph_state = 2;
-  }
+  const int rc = run_steps(c, first_step, n_steps);
+  if (rc) return rc;
   // a step that raised a flag ended at a barrier and every later launch did nothing
   return n_steps > 0 ? consume_flags(c) : SCO_OK;
 }
+
 
 int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* dev_spins_in,
                     int8_t* dev_spins_out, uint64_t first_step, int n_steps, sco_obs* host_obs, void* stream) {
@@ -808,15 +831,23 @@ void graph_release(sco_ctx* c) {
 
 // A graph of n full-step kernel nodes, each depending on the one before, every node
 // a cooperative launch of the schedule's grid.
-int graph_build(sco_ctx* c, int n) {
+// the phases of node k of the step graph (one node per step, or three)
+uint32_t graph_node_phases(const sco_ctx* c, int k) {
+  if (c->step_fused) return PH_SWITCH | PH_COLOR | PH_SWEEP;
+  const uint32_t ph[3] = {PH_SWITCH, PH_COLOR, PH_SWEEP};
+  return ph[k % 3];
+}
+
+int graph_build(sco_ctx* c, int n_steps) {
   graph_release(c);
   if (hipGraphCreate(&c->graph, 0) != hipSuccess) return SCO_EHIP;
+  const int n = n_steps * (c->step_fused ? 1 : 3);
   c->graph_nodes.resize(n);
   c->graph_args.assign(n, c->args);
   for (int s = 0; s < n; ++s) {
     void* kargs[] = {&c->graph_args[s]};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(sco_dev::step_kernel_full(c->model));
+    kp.func = const_cast<void*>(sco_dev::step_kernel_for(graph_node_phases(c, s), c->model));
     kp.gridDim = dim3(c->blocks);
     kp.blockDim = dim3(SCO_CHUNK);
     kp.sharedMemBytes = 0;
@@ -847,7 +878,8 @@ int sco_run_graph(sco_ctx* c, uint64_t first_step, int n_steps) {
   if (!c || n_steps < 0) return SCO_EINVAL;
   if (n_steps == 0) return SCO_OK;
   if (first_step + static_cast<uint64_t>(n_steps) - 1 > 0xFFFFFFFFull) return SCO_EINVAL;
-  if (!c->graph_exec || static_cast<int>(c->graph_nodes.size()) != n_steps || c->graph_blocks != c->blocks) {
+  const int per = c->step_fused ? 1 : 3;
+  if (!c->graph_exec || static_cast<int>(c->graph_nodes.size()) != n_steps * per || c->graph_blocks != c->blocks) {
     const int rc = graph_build(c, n_steps);
     if (rc) return rc;
   }
@@ -856,24 +888,31 @@ int sco_run_graph(sco_ctx* c, uint64_t first_step, int n_steps) {
     c->launched_blocks = c->blocks;
   }
   // this replay's step indices (and the current tile limit) into the nodes' arguments
-  for (int s = 0; s < n_steps; ++s) {
-    StepArgs& a = c->graph_args[s];
+  for (int k = 0; k < n_steps * per; ++k) {
+    StepArgs& a = c->graph_args[k];
     a = c->args;
     a.trace = nullptr;
     a.nsw_override = -1;
     a.nsw_max = c->nsw_max;
-    a.step = static_cast<uint32_t>(first_step + static_cast<uint64_t>(s));
+    a.step = static_cast<uint32_t>(first_step + static_cast<uint64_t>(k / per));
     void* kargs[] = {&a};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(sco_dev::step_kernel_full(c->model));
+    kp.func = const_cast<void*>(sco_dev::step_kernel_for(graph_node_phases(c, k), c->model));
     kp.gridDim = dim3(c->blocks);
     kp.blockDim = dim3(SCO_CHUNK);
     kp.kernelParams = kargs;
-    HIP_TRY(hipGraphExecKernelNodeSetParams(c->graph_exec, c->graph_nodes[s], &kp));
+    HIP_TRY(hipGraphExecKernelNodeSetParams(c->graph_exec, c->graph_nodes[k], &kp));
   }
   HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
   c->graph_state = 2;
   return consume_flags(c);
+}
+
+int sco_set_step_form(sco_ctx* c, int fused) {
+  if (!c || fused < 0 || fused > 1) return SCO_EINVAL;
+  if (c->step_fused != fused) graph_release(c);
+  c->step_fused = fused;
+  return SCO_OK;
 }
 
 int sco_set_temperature(sco_ctx* c, int chain, double T) {

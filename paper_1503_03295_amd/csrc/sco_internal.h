@@ -151,6 +151,7 @@ int step_max_blocks();
 hipError_t step(hipStream_t s, const StepArgs& a, uint32_t phases, int blocks, int model);
 // The full step kernel of a model, for graph kernel nodes.
 const void* step_kernel_full(int model);
+const void* step_kernel_for(uint32_t phases, int model);
 // Heisenberg observables: prod[m] = sum over owners of the pair energy of displacement
 // m; part2[b] = per-block (exchange sum, M_phi sum); out2 = their totals
 hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& hd, const double* spin3,

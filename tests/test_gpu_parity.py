@@ -68,6 +68,30 @@ def test_several_sweeps_after_device_wide_levels(kappa):
     log(f"  tolerated near ties: {out['tolerated']}")
 
 
+def test_step_forms_give_identical_chains():
+    """A step as three phase launches (the default) and as one fused launch: same
+    spins, bond graph, colours and counters, by plain launches and graph replays."""
+    from paper_1503_03295_amd import SCO
+
+    params = [workloads.chain(256, True, 1.2, 2.0, chain_id=0, n_sw=2),
+              workloads.chain(40, False, 0.9, 1.0, chain_id=1)]
+    a = SCO([gpu_params(p) for p in params], device="cuda:0")
+    b = SCO([gpu_params(p) for p in params], device="cuda:0")
+    b.set_step_form(True)
+    a.run(0, 3)
+    b.run(0, 3)
+    a.run_graph(3, 2)
+    b.run_graph(3, 2)
+    for c in range(len(params)):
+        np.testing.assert_array_equal(a.spins(c), b.spins(c))
+        for x, y in zip(a.graph(c), b.graph(c)):
+            np.testing.assert_array_equal(x, y)
+    for x, y in zip(a.counters(), b.counters()):
+        for k in ("M", "n_edges", "q", "kw_rounds", "accepted", "attempts", "near_ties"):
+            assert x[k] == y[k], k
+    assert all(t > 0 for t in a.phase_times())  # the last step's phases are timed
+
+
 def test_fenced_sweeps_match_oracle():
     """The documented release/acquire barrier after every colour class gives the same
     chains as the light class barrier (a ragged batch, three sweeps per step)."""
