@@ -262,7 +262,8 @@ int sco_get_flags(sco_ctx* ctx, int64_t* last, int64_t* seen);
  * exact integer pair correlation C_m of each half-displacement, from a number-theoretic
  * transform of the spins (O(N log N); lattice sizes with a prime factor above 7 take a
  * direct O(N K / 32) count); Heisenberg chains: E_exchange, E_dipolar (the full tensor
- * of Eq. 6, O(N K)) and m_phi of Eq. (7).  n_edges, delta_union, q and the colours are
+ * of Eq. 6: direct pair sums while N K <= 2e9, above that FP64 FFT correlations of the
+ * spin components, O(N log N)) and m_phi of Eq. (7).  n_edges, delta_union, q and the colours are
  * the graph statistics of Sec. 3.2 (mean degree 2 n_edges / N) for the last switching
  * and colouring. */
 int sco_observables(sco_ctx* ctx, sco_obs* host_out);

@@ -115,6 +115,32 @@ NttPlan ntt_plan(const sco_chain_params& q) {
   pl.ninv2 = static_cast<uint32_t>(static_cast<uint64_t>(ninv) * ninv % p);
   return pl;
 }
+// The FP64 transforms of a Heisenberg chain's dipolar energy: length the smallest
+// 2^a 3^b 5^c 7^d >= 2L - 1 (open lattice, zero-padded); n = 0 (the direct pair sums)
+// while N K <= 2e9, where those take at most about a second.
+NttPlan fft_plan(const sco_chain_params& q) {
+  NttPlan pl{};
+  if (q.model != SCO_MODEL_HEIS) return pl;
+  const double L = q.L;
+  if (L * L * 2.0 * L * (L - 1.0) <= 2e9) return pl;
+  int n = 0;
+  for (n = 2 * q.L - 1; n < 8 * q.L; ++n)
+    if (ntt_radices(n, pl)) break;
+  if (n > 16384) return NttPlan{};
+  pl.n = n;
+  return pl;
+}
+// (cos, sin)(2 pi e / n), e < n
+std::vector<double> fft_twiddles(int n) {
+  std::vector<double> tw(2 * static_cast<size_t>(n));
+  const double step = 2.0 * 3.14159265358979323846 / static_cast<double>(n);
+  for (int e = 0; e < n; ++e) {
+    tw[2 * e] = std::cos(step * e);
+    tw[2 * e + 1] = std::sin(step * e);
+  }
+  return tw;
+}
+
 // w^e in Montgomery form, e < n, w a primitive n-th root of unity mod p
 std::vector<uint32_t> ntt_twiddles(const NttPlan& pl) {
   const uint32_t p = pl.p;
@@ -158,6 +184,7 @@ struct Layout {
   size_t off_agg = 0, off_obs = 0, off_used = 0, off_bits = 0, off_prod = 0, off_dpart = 0, off_dres = 0;
   size_t off_acc = 0, off_spin3 = 0, off_hpart = 0, off_hres = 0, off_csz = 0;
   size_t off_ntt = 0, off_tw = 0;  // transform buffers (2 n^2) and twiddles (n) of the largest plan
+  size_t off_fft = 0, off_ftw = 0;  // Heisenberg: FP64 transform buffers (3 n^2 complex), twiddles
   int64_t G = 0, nchunks = 0, ntiles = 0, maxK = 0;
   uint32_t cap_und = 0;
   size_t bytes = 0;
@@ -256,6 +283,10 @@ int make_layout(const sco_chain_params* p, int n, Layout& lay) {
   for (int c = 0; c < n; ++c) nmax = std::max<int64_t>(nmax, ntt_plan(p[c]).n);
   lay.off_ntt = take(sizeof(uint32_t) * 2 * nmax * nmax);
   lay.off_tw = take(sizeof(uint32_t) * nmax);
+  int64_t fmax = 0;
+  for (int c = 0; c < n; ++c) fmax = std::max<int64_t>(fmax, fft_plan(p[c]).n);
+  lay.off_fft = take(2 * sizeof(double) * 3 * fmax * fmax);
+  lay.off_ftw = take(2 * sizeof(double) * fmax);
   lay.bytes = off;
   return SCO_OK;
 }
@@ -1329,9 +1360,16 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   for (int ci = 0; ci < c->n && (dipolar || heis); ++ci) {
     const ChainDesc& d = c->cd[ci];
     if (heis) {
+      const NttPlan fp = dipolar ? fft_plan(c->params[ci]) : NttPlan{};
+      if (fp.n > 0) {
+        const std::vector<double> tw = fft_twiddles(fp.n);
+        HIP_TRY(hipMemcpyAsync(at<double>(c, L.off_ftw), tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice,
+                               c->stream));
+      }
       HIP_TRY(sco_dev::obs_heis(c->stream, at<ChainDesc>(c, L.off_cd), ci, d, at<double>(c, L.off_spin3),
                                 at<double>(c, L.off_prod), at<double>(c, L.off_dpart), at<double>(c, L.off_dres) + ci,
-                                at<double>(c, L.off_hpart), at<double>(c, L.off_hres)));
+                                at<double>(c, L.off_hpart), at<double>(c, L.off_hres), dipolar, &fp,
+                                at<double2>(c, L.off_fft), at<double2>(c, L.off_ftw)));
       HIP_TRY(hipMemcpyAsync(&hres[2 * ci], at<double>(c, L.off_hres), 2 * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1357,7 +1395,7 @@ int observables_impl(sco_ctx* c, sco_obs* out, bool dipolar) {
   HIP_TRY(hipMemcpyAsync(st.data(), at<ChainState>(c, L.off_st), sizeof(ChainState) * c->n, hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(sums.data(), d_obs, sizeof(unsigned long long) * 2 * c->n, hipMemcpyDeviceToHost, c->stream));
-  if (dipolar || heis)
+  if (dipolar)
     HIP_TRY(hipMemcpyAsync(edip.data(), at<double>(c, L.off_dres), sizeof(double) * c->n, hipMemcpyDeviceToHost,
                            c->stream));
   else

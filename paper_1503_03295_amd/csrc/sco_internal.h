@@ -154,8 +154,9 @@ const void* step_kernel_full(int model);
 const void* step_kernel_for(uint32_t phases, int model);
 // Heisenberg observables: prod[m] = sum over owners of the pair energy of displacement
 // m; part2[b] = per-block (exchange sum, M_phi sum); out2 = their totals
-hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& hd, const double* spin3,
-                    double* prod, double* part, double* out, double* part2, double* out2);
+hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& h, const double* spin3,
+                    double* prod, double* part, double* out, double* part2, double* out2, bool dipolar,
+                    const NttPlan* fft, double2* fbuf, const double2* ftw);
 hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_chain,
                      const int8_t* spin, const uint16_t* color, unsigned long long* out,
                      unsigned* used, int64_t G);

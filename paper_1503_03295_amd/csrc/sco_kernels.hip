@@ -3341,6 +3341,130 @@ extern "C" __global__ void k_ntt_gather(const uint32_t* __restrict__ cn, int n, 
   prod[m] = J[m] * static_cast<double>(c);
 }
 
+// ------------------------------------------- Heisenberg dipolar energy by FP64 FFTs
+// E_dip = sum over the owned pairs of (J_m / 2) [S_i . S_j - 3 (S_i . d)(S_j . d) / r^2]
+// (Eq. 6, J_m = 2 D / r^3) needs, per displacement d, the correlations
+// C_ab(d) = sum_i S_i^a S_{i+d}^b of the spin components: S . S = C_xx + C_yy + C_zz
+// and (S_i . d)(S_j . d) = dx^2 C_xx + dx dy (C_xy + C_yx) + dy^2 C_yy.  They come from
+// complex FP64 transforms of the zero-padded n x n component arrays (n >= 2L - 1, so
+// the cyclic correlations are the open lattice's): Z1 = FFT(S^x + i S^y), Z2 = FFT(S^z);
+// F_x, F_y separate by the symmetry of real inputs, and the real, even spectra
+// |F_x|^2 + |F_y|^2 + |F_z|^2, |F_x|^2, |F_y|^2, 2 Re(conj F_x F_y) go back two per
+// inverse transform (real and imaginary parts).  Stockham passes as for the exact
+// transform; tw[e] = (cos, sin)(2 pi e / n).
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// spins (one chain, 3 doubles per site) into Z1 = S^x + i S^y and Z2 = S^z, zero-padded
+extern "C" __global__ void k_fft_load3(const double* __restrict__ s3, int L, int n, double2* __restrict__ z1,
+                                       double2* __restrict__ z2) {
+  const int64_t t = gtid();
+  if (t >= static_cast<int64_t>(n) * n) return;
+  const int y = static_cast<int>(t / n), x = static_cast<int>(t - static_cast<int64_t>(y) * n);
+  double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+  if (x < L && y < L) {
+    const double* S = s3 + 3 * (static_cast<int64_t>(y) * L + x);
+    a = make_double2(S[0], S[1]);
+    b.x = S[2];
+  }
+  z1[t] = a;
+  z2[t] = b;
+}
+
+// One Stockham pass of radix R (forward: e^{-2 pi i / n}; inv: e^{+2 pi i / n}, unscaled)
+template <int R>
+__global__ void k_fft_pass(const double2* __restrict__ in, double2* __restrict__ out, int n, int Ns, int dim,
+                           const double2* __restrict__ tw, int inv) {
+  const int64_t t = gtid();
+  const int m = n / R;
+  if (t >= static_cast<int64_t>(n) * m) return;
+  int line, j;
+  if (dim == 0) {
+    line = static_cast<int>(t / m);
+    j = static_cast<int>(t - static_cast<int64_t>(line) * m);
+  } else {
+    j = static_cast<int>(t / n);
+    line = static_cast<int>(t - static_cast<int64_t>(j) * n);
+  }
+  auto at = [&](int x) -> int64_t {
+    return dim == 0 ? static_cast<int64_t>(line) * n + x : static_cast<int64_t>(x) * n + line;
+  };
+  auto w = [&](int e) {  // w^e of the transform's direction
+    const double2 c = tw[e];
+    return inv ? c : make_double2(c.x, -c.y);
+  };
+  const int k = j % Ns;
+  const int step = n / (Ns * R);
+  double2 a[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double2 v = in[at(j + q * m)];
+    a[q] = q == 0 ? v : cmul(v, w(step * k * q));
+  }
+  const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    double2 acc = a[0];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      const double2 c = cmul(a[q], w(static_cast<int>((static_cast<int64_t>(m) * q * u) % n)));
+      acc.x += c.x;
+      acc.y += c.y;
+    }
+    out[at(base + u * Ns)] = acc;
+  }
+}
+
+// The four spectra from Z1, Z2, in place, one thread per pair {k, -k}:
+// Z1 <- |F_x|^2 + |F_y|^2 + |F_z|^2 + i |F_x|^2,  Z2 <- |F_y|^2 + i 2 Re(conj F_x F_y),
+// F_x(k) = (Z1(k) + conj Z1(-k)) / 2, F_y(k) = (Z1(k) - conj Z1(-k)) / 2i
+extern "C" __global__ void k_fft_spectra(double2* __restrict__ z1, double2* __restrict__ z2, int n) {
+  const int64_t t = gtid();
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  if (t >= nn) return;
+  const int ky = static_cast<int>(t / n), kx = static_cast<int>(t - static_cast<int64_t>(ky) * n);
+  const int64_t tm = static_cast<int64_t>(ky ? n - ky : 0) * n + (kx ? n - kx : 0);
+  if (tm < t) return;  // the pair's other member does both
+  auto spectra = [](double2 zk, double2 zmk, double2 z2k, double2& o1, double2& o2) {
+    const double fxr = 0.5 * (zk.x + zmk.x), fxi = 0.5 * (zk.y - zmk.y);
+    const double fyr = 0.5 * (zk.y + zmk.y), fyi = -0.5 * (zk.x - zmk.x);
+    const double pxx = fxr * fxr + fxi * fxi, pyy = fyr * fyr + fyi * fyi;
+    const double pzz = z2k.x * z2k.x + z2k.y * z2k.y;
+    o1 = make_double2(pxx + pyy + pzz, pxx);
+    o2 = make_double2(pyy, 2.0 * (fxr * fyr + fxi * fyi));
+  };
+  const double2 a = z1[t], b = z1[tm], ca = z2[t], cb = z2[tm];
+  double2 o1, o2, p1, p2;
+  spectra(a, b, ca, o1, o2);
+  spectra(b, a, cb, p1, p2);
+  z1[t] = o1;
+  z2[t] = o2;
+  if (tm != t) {
+    z1[tm] = p1;
+    z2[tm] = p2;
+  }
+}
+
+// prod[m] = (J_m / 2) [S(d) - 3 (dx^2 C_xx + dx dy (C_xy + C_yx) + dy^2 C_yy) / r^2] from
+// the inverse transforms (n^2 times the correlations)
+extern "C" __global__ void k_fft_gather_heis(const double2* __restrict__ w1, const double2* __restrict__ w2,
+                                             int n, const uint32_t* __restrict__ hd, const double* __restrict__ J,
+                                             int K, double* __restrict__ prod) {
+  const int64_t m = gtid();
+  if (m >= K) return;
+  const uint32_t hp = hd[m];
+  const int dx = static_cast<int16_t>(hp & 0xFFFFu), dy = static_cast<int16_t>(hp >> 16);
+  const int64_t idx = static_cast<int64_t>(dy < 0 ? dy + n : dy) * n + (dx < 0 ? dx + n : dx);
+  const double inv = 1.0 / (static_cast<double>(n) * static_cast<double>(n));
+  const double2 a = w1[idx], b = w2[idx];
+  const double sdot = a.x * inv, cxx = a.y * inv, cyy = b.x * inv, cxy = b.y * inv;
+  const double fx = static_cast<double>(dx), fy = static_cast<double>(dy);
+  const double r2 = fx * fx + fy * fy;
+  prod[m] = (J[m] * 0.5) * (sdot - 3.0 * (fx * fx * cxx + fx * fy * cxy + fy * fy * cyy) / r2);
+}
+
 // Same quantity for any L, pair by pair (small lattices).
 extern "C" __global__ void k_obs_corr_plain(const uint32_t* __restrict__ hd, const double* __restrict__ J,
                                             int K, int L, int periodic, const int8_t* __restrict__ spin,
@@ -3481,14 +3605,62 @@ hipError_t obs_basic(hipStream_t s, const ChainDesc* cd, const int32_t* chunk_ch
 }
 
 hipError_t obs_heis(hipStream_t s, const ChainDesc* cd, int chain, const ChainDesc& h, const double* spin3,
-                    double* prod, double* part, double* out, double* part2, double* out2) {
+                    double* prod, double* part, double* out, double* part2, double* out2, bool dipolar,
+                    const NttPlan* fft, double2* fbuf, const double2* ftw) {
   (void)cd;
   (void)chain;
   const double* s3 = spin3 + 3 * h.vbase;
-  hipLaunchKernelGGL(k_obs_heis_pairs, dim3((h.K + 255) / 256), dim3(256), 0, s, h.hd, h.J, h.K, h.L, s3, prod);
-  const int nparts = (h.K + 4095) / 4096;
-  hipLaunchKernelGGL(k_obs_sum_partials, dim3(nparts), dim3(256), 0, s, prod, h.K, part);
-  hipLaunchKernelGGL(k_obs_sum_final, dim3(1), dim3(64), 0, s, part, nparts, out);
+  if (!dipolar) {
+    // the site sums only (exchange, M_phi)
+  } else if (fft && fft->n > 0) {
+    const int n = fft->n;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    const dim3 g1(static_cast<uint32_t>((nn + 255) / 256));
+    double2* buf[3] = {fbuf, fbuf + nn, fbuf + 2 * nn};  // Z1, Z2, scratch
+    hipLaunchKernelGGL(k_fft_load3, g1, dim3(256), 0, s, s3, h.L, n, buf[0], buf[1]);
+    // a 2-D transform of buf[which], ping-ponging with the scratch; the result ends in buf[which]
+    auto transform = [&](int which, int inv) {
+      double2* A = buf[which];
+      double2* B = buf[2];
+      for (int dim = 0; dim < 2; ++dim) {
+        int Ns = 1;
+        for (int i = 0; i < fft->nrad; ++i) {
+          const int r = fft->rad[i];
+          const dim3 g(static_cast<uint32_t>((nn / r + 255) / 256));
+          switch (r) {
+            case 2: hipLaunchKernelGGL(k_fft_pass<2>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+            case 3: hipLaunchKernelGGL(k_fft_pass<3>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+            case 4: hipLaunchKernelGGL(k_fft_pass<4>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+            case 5: hipLaunchKernelGGL(k_fft_pass<5>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+            case 7: hipLaunchKernelGGL(k_fft_pass<7>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+            default: hipLaunchKernelGGL(k_fft_pass<8>, g, dim3(256), 0, s, A, B, n, Ns, dim, ftw, inv); break;
+          }
+          Ns *= r;
+          double2* x = A;
+          A = B;
+          B = x;
+        }
+      }
+      if (A != buf[which]) {  // an odd number of passes: the result is in the scratch
+        buf[2] = buf[which];
+        buf[which] = A;
+      }
+    };
+    transform(0, 0);
+    transform(1, 0);
+    hipLaunchKernelGGL(k_fft_spectra, g1, dim3(256), 0, s, buf[0], buf[1], n);
+    transform(0, 1);
+    transform(1, 1);
+    hipLaunchKernelGGL(k_fft_gather_heis, dim3((h.K + 255) / 256), dim3(256), 0, s, buf[0], buf[1], n, h.hd, h.J,
+                       h.K, prod);
+  } else {
+    hipLaunchKernelGGL(k_obs_heis_pairs, dim3((h.K + 255) / 256), dim3(256), 0, s, h.hd, h.J, h.K, h.L, s3, prod);
+  }
+  if (dipolar) {
+    const int nparts = (h.K + 4095) / 4096;
+    hipLaunchKernelGGL(k_obs_sum_partials, dim3(nparts), dim3(256), 0, s, prod, h.K, part);
+    hipLaunchKernelGGL(k_obs_sum_final, dim3(1), dim3(64), 0, s, part, nparts, out);
+  }
   const int nb = (h.N + 255) / 256;
   hipLaunchKernelGGL(k_obs_heis_site, dim3(nb), dim3(256), 0, s, s3, h.L, part2);
   hipLaunchKernelGGL(k_obs_heis_site_final, dim3(1), dim3(64), 0, s, part2, nb, out2);
