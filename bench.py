@@ -200,14 +200,20 @@ def heisenberg_leg(torch, SCO, ChainParams, L=2304, T=1.25, n_sw=100, warm=3, st
     sco.sweep(t, n_sw)
     ph = sco.phase_times()
     o = sco.counters()[0]
+    t_obs = time.perf_counter()
+    full = sco.observables()[0]  # the full dipolar tensor energy by FFT correlations
+    t_obs = time.perf_counter() - t_obs
     N = L * L
     out = {"L": L, "T": T, "n_sw": n_sw, "steps": steps, "ms_per_step": ms,
            "attempts_per_s": N * n_sw / (ms / 1e3),
            "phase_ms": {"switch": ph[0], "color": ph[1], "sweep": ph[2]},
            "k_mean": 2.0 * o["n_edges"] / N, "delta_sco": o["delta_sco"], "q": o["q"],
-           "acceptance": o["accepted"] / max(1, o["attempts"])}
+           "acceptance": o["accepted"] / max(1, o["attempts"]),
+           "E_per_site": full["E"] / N, "E_dipolar_per_site": full["E_dipolar"] / N, "m_phi": full["m_phi"],
+           "observables_ms": 1e3 * t_obs}
     progress(f"heisenberg L={L} T={T}: {ms:.2f} ms/step, {out['attempts_per_s']:.4g} attempts/s, "
-             f"<k> {out['k_mean']:.3f}, Delta {o['delta_sco']}")
+             f"<k> {out['k_mean']:.3f}, Delta {o['delta_sco']}, E/N {out['E_per_site']:.6f}, "
+             f"M_phi {out['m_phi']:.3g} ({out['observables_ms']:.1f} ms)")
     sco.close()
     return out
 
