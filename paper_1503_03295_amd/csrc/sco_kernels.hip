@@ -328,7 +328,7 @@ __device__ __forceinline__ bool class_barrier(SyncWords* s) {
   return s_ok != 0;
 }
 
-// Sum / max over a block (all threads must call); result valid in every thread.
+// Sum over a block (all threads must call); result valid in every thread.
 template <typename T>
 __device__ T block_sum(T v) {
   __shared__ T red[kWaves];
@@ -338,17 +338,6 @@ __device__ T block_sum(T v) {
   __syncthreads();
   T t = 0;
   for (int i = 0; i < kWaves; ++i) t += red[i];
-  return t;
-}
-
-__device__ int block_max(int v) {
-  __shared__ int red[kWaves];
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int t = 0;
-  for (int i = 0; i < kWaves; ++i) t = max(t, red[i]);
   return t;
 }
 
