@@ -50,7 +50,7 @@ def phase_bytes(N, E, c, M, P, k_mean, hard, n_sw, accept):
       switch    per owner: its spin (1) + the partner spin of each candidate (c) +
                 its survivor count (4)
       assembly  per site: degree scan read + write (8); per survivor s = E/N:
-                both directions (2 x 8) + cursor atomics (4) + row sort read/write (16)
+                both directions (2 x 8) + the partner count (4) + row sort read/write (16)
       colour    per pending site and level run over the whole lattice (M - P levels,
                 N/2 pending each): row_ptr (4) + bond partners (4k) + neighbour
                 words (4 + k) + the decision (2); the P levels held in LDS count once

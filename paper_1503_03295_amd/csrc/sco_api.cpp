@@ -728,6 +728,7 @@ int init_impl(sco_ctx** out, const sco_chain_params* params, int n_chains, void*
   a.deg = at<int32_t>(c, L.off_deg);
   a.row_ptr = at<int32_t>(c, L.off_row);
   a.fill = at<int32_t>(c, L.off_fill);
+  a.own = reinterpret_cast<uint16_t*>(a.fill);
   a.ea = at<int32_t>(c, L.off_ea);
   a.eb = at<int32_t>(c, L.off_eb);
   a.em = at<int32_t>(c, L.off_em);

@@ -99,11 +99,14 @@ struct StepArgs {
   const int32_t* chunk_chain;
   int8_t* spin;
   double* spin3;          // [3 G] Heisenberg spins (x, y, z per site), nullptr for Ising
-  int32_t* deg;           // [G] degrees (cleared by the switching phase)
+  int32_t* deg;           // [G] survivors with the site as partner (cleared by the switching phase)
   int32_t* row_ptr;       // [G + 1]
-  int32_t* fill;          // [G] scatter cursors: cleared, then set to each owner's survivor count
+  int32_t* fill;          // [G] the whole-graph colour reduction's dependence counts
+  uint16_t* own;          // [G] survivors with the site as owner (every site written by the
+                          // switching; aliases fill, which the colouring alone uses)
   int32_t *ea, *eb, *em;  // survivors: owner, partner (global sites), displacement index
-  int32_t* er;            // survivor's rank among its owner's survivors
+  int32_t* er;            // survivor's rank among its owner's survivors | its slot among
+                          // its partner's incoming survivors << 16 (as uint32_t)
   int32_t* col;           // [2 * cap] neighbour (global site)
   int32_t* attr;          // [2 * cap] displacement index
   uint16_t* color;        // [G]

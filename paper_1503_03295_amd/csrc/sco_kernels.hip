@@ -9,7 +9,8 @@
 //                             appended with one atomic per wavefront (ballot count)
 //             scan_two_pass   prefix sum of the degrees (row offsets): tile sums, one
 //                             device barrier, then every tile scanned in LDS
-//             phase_scatter   both directions of every survivor into the CSR
+//             phase_scatter   both directions of every survivor into the CSR, at
+//                             slots fixed in the switching (no atomics)
 //             phase_rowsort   rows ascending by neighbour, union degree, Delta
 //   step (2)  phase_kw_local  Kuhn-Wattenhofer levels whose groups fit in one LDS tile
 //             phase_kw_global the remaining levels, colour class by colour class
@@ -898,6 +899,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
             const W4 r = philox10(step, static_cast<uint32_t>(v), 0u, SCO_TAG_SW, d.seed, d.chain_id);
             keep = !(unit52(r.x, r.y) < d.u_first_end);
           }
+          if (!keep) a.own[g] = 0;  // an owner with no survivor (or padding)
         }
         const uint64_t m = __ballot(keep);
         if (m != 0) {
@@ -984,13 +986,14 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       int jc[kOwners], mc[kOwners], sc[kOwners], xc[kOwners], yc[kOwners];
       double bx[kOwners], by[kOwners], bz[kOwners];
       uint32_t kc[kOwners];
-      bool cc[kOwners];
+      bool cc[kOwners], fin[kOwners];
 #pragma unroll
       for (int u = 0; u < kOwners; ++u) {
         jc[u] = -1;
         mc[u] = 0;
         kc[u] = 0;
         xc[u] = yc[u] = 0;
+        const bool was_live = O[u].live;
         bool park = false;
         cc[u] = O[u].live &&
                 owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], may_park, park);
@@ -1004,11 +1007,14 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
             parked[3 * idx + 2] = make_int4(o.ns, 0, 0, 0);
             O[u].live = false;
             O[u].ns = 0;
+            fin[u] = false;  // not ended: resumed in the second pass
+            continue;
           } else {  // no room: this draw in FP64 now
             bool again = false;
             cc[u] = owner_candidate(a, desc_of, tb, step, O[u], jc[u], mc[u], kc[u], tally, xc[u], yc[u], false, again);
           }
         }
+        fin[u] = was_live && !O[u].live;
       }
 #pragma unroll
       for (int u = 0; u < kOwners; ++u) {
@@ -1034,11 +1040,12 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
           f = cc[u] && owner_survives(desc_of, step, O[u], jc[u], mc[u], kc[u], sc[u]);
         O[u].ns = append(f, O[u].g, O[u].v, jc[u], mc[u], O[u].ns);
       }
-      // an ended owner's survivor count starts its row's cursor for the partners
+      // an ended owner's survivor count: the front of its row
 #pragma unroll
       for (int u = 0; u < kOwners; ++u) {
-        if (!O[u].live && O[u].ns) {
-          a.fill[O[u].g] = O[u].ns;
+        if (fin[u]) {
+          if (O[u].ns > 0xFFFF) set_flag(a.sync, SCO_FLAG_OVERFLOW);
+          a.own[O[u].g] = static_cast<uint16_t>(O[u].ns);
           O[u].ns = 0;
         }
         take(O[u], !O[u].live && pool);
@@ -1077,12 +1084,34 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     }
   }
   __syncthreads();
-  // the degrees, from the block's survivor list: the atomics are issued after the
-  // draws, so no load of the draw loop waits behind them
+  // the partners' counts, from the block's survivor list (issued after the draws, so
+  // no load of the draw loop waits behind them): the count before a survivor's
+  // increment is its slot among its partner's incoming survivors, kept beside its rank
   const uint32_t ne = min(s_count, cap_blk);
-  for (uint32_t e = threadIdx.x; e < ne; e += kBlock) {
-    atomicAdd(&a.deg[a.ea[e_base + e]], 1);
-    atomicAdd(&a.deg[a.eb[e_base + e]], 1);
+  uint32_t* const er = reinterpret_cast<uint32_t*>(a.er) + e_base;
+  for (uint32_t e0 = 0; e0 < ne; e0 += kScan * kBlock) {
+    int32_t pj[kScan];
+    uint32_t rk[kScan];
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) {
+      const uint32_t e = e0 + r * kBlock + threadIdx.x;
+      pj[r] = -1;
+      rk[r] = 0;
+      if (e < ne) {
+        pj[r] = a.eb[e_base + e];
+        rk[r] = er[e];
+      }
+    }
+    int32_t sl[kScan];
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) sl[r] = pj[r] >= 0 ? atomicAdd(&a.deg[pj[r]], 1) : 0;
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) {
+      const uint32_t e = e0 + r * kBlock + threadIdx.x;
+      if (pj[r] < 0) continue;
+      if (sl[r] > 0xFFFF || rk[r] > 0xFFFFu) set_flag(a.sync, SCO_FLAG_OVERFLOW);
+      er[e] = (rk[r] & 0xFFFFu) | (static_cast<uint32_t>(sl[r]) << 16);
+    }
   }
   if (threadIdx.x == 0)
     for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? ne : 0u;
@@ -1090,7 +1119,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
 }
 
 // ------------------------------------------------------------------ prefix sum
-// Exclusive scan of n int32 values in tiles of kTile: (1) every block sums its tiles
+// Exclusive scan of the n sums in[i] + in2[i] in tiles of kTile: (1) every block sums its tiles
 // into agg[t]; (2) a device-wide barrier; (3) each block adds the sums of the tiles
 // before each of its tiles and scans the tile.  Global memory is read and written in
 // coalesced rows (item k * kBlock + thread); the scan order goes through LDS, padded
@@ -1099,8 +1128,8 @@ constexpr int kItems = SCO_SCAN_ITEMS;  // one tile per block at L = 2304 on 256
 constexpr int kTile = kBlock * kItems;
 constexpr int kScanLds = kTile + kTile / 32;  // words of the padded tile in LDS
 
-__device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, int32_t* out, long long* agg,
-                                              int32_t* lds, SyncWords* sync) {
+__device__ __forceinline__ bool scan_two_pass(const int32_t* in, const uint16_t* in2, int64_t n64, int32_t* out,
+                                              long long* agg, int32_t* lds, SyncWords* sync) {
   __shared__ int32_t wsum[kWaves];
   const int n = static_cast<int>(n64);  // G < 2^31
   const int nt = (n + kTile - 1) / kTile;
@@ -1118,7 +1147,7 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, in
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const int idx = tb + k * kBlock;
-      s += idx < n ? in[idx] : 0;
+      s += idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0;
     }
     s = block_sum(s);
     if (threadIdx.x == 0) agg[t] = s;
@@ -1130,7 +1159,7 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, int64_t n64, in
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const int idx = tb + k * kBlock;
-      lds[rowb + k * kRow] = idx < n ? in[idx] : 0;
+      lds[rowb + k * kRow] = idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0;
     }
     // sum of the tiles before t
     long long pre = 0;
@@ -1175,8 +1204,7 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
   const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
   for (int ch = ch0; ch < ch1; ++ch) {
     const uint32_t e0 = static_cast<uint32_t>(ch) * cap_chunk, e1 = e0 + a.ecount[ch];
-    // kScan survivors per thread and iteration, their loads and cursor atomics
-    // issued together
+    // kScan survivors per thread and iteration, their loads issued together
     for (uint32_t eb = e0; eb < e1; eb += kScan * kBlock) {
       int32_t u[kScan], w[kScan], m[kScan], rk[kScan];
       bool ok[kScan];
@@ -1192,15 +1220,16 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
           rk[r] = a.er[e];
         }
       }
-      // the owner's entries first, at their rank; the partners' after them, through
-      // the cursor that starts at the owner's survivor count
+      // the owner's entries at the front of its row, at their rank; the partner's
+      // incoming entries from the back of its row, at their slot
       int64_t pu[kScan], pw[kScan];
 #pragma unroll
       for (int r = 0; r < kScan; ++r) {
         pu[r] = pw[r] = -1;
         if (ok[r]) {
-          pu[r] = static_cast<int64_t>(a.row_ptr[u[r]]) + rk[r];
-          pw[r] = a.row_ptr[w[r]] + atomicAdd(&a.fill[w[r]], 1);
+          const uint32_t rs = static_cast<uint32_t>(rk[r]);
+          pu[r] = static_cast<int64_t>(a.row_ptr[u[r]]) + (rs & 0xFFFFu);
+          pw[r] = static_cast<int64_t>(a.row_ptr[w[r] + 1]) - 1 - (rs >> 16);
         }
       }
 #pragma unroll
@@ -2453,17 +2482,20 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
     };
     if constexpr (staged) {
       // own range, four sites per word read (the range and the chain start on chunk
-      // bounds); a site has bonds when its degree is not zero
+      // bounds); a site has bonds when its row is not empty
       uint32_t sw[kStageSw];
       int4 dg[kStageSw];
+      int32_t rn[kStageSw];
 #pragma unroll
       for (int r = 0; r < kStageSw; ++r) {
         const int w = r * kBlock + tid;
         sw[r] = 0u;
         dg[r] = make_int4(0, 0, 0, 0);
+        rn[r] = 0;
         if (4 * w < n_own) {
           sw[r] = ld_relaxed(reinterpret_cast<const uint32_t*>(a.spin + r0) + w);
-          dg[r] = reinterpret_cast<const int4*>(a.deg + r0)[w];
+          dg[r] = reinterpret_cast<const int4*>(a.row_ptr + r0)[w];
+          rn[r] = a.row_ptr[r0 + 4 * w + 4];
         }
       }
       load_halo();
@@ -2471,7 +2503,7 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
       for (int r = 0; r < kStageSw; ++r) {
         const int w = r * kBlock + tid;
         if (4 * w < n_own) {
-          const int dd[4] = {dg[r].x, dg[r].y, dg[r].z, dg[r].w};
+          const int dd[4] = {dg[r].y - dg[r].x, dg[r].z - dg[r].y, dg[r].w - dg[r].z, rn[r] - dg[r].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int8_t sp = static_cast<int8_t>((sw[r] >> (8 * i)) & 0xFFu);
@@ -2872,7 +2904,7 @@ __device__ __forceinline__ bool phase_sweep_heis(const StepArgs& a, uint32_t ste
 // ------------------------------------------------------------------ the step
 // Persistent kernel (cooperative launch: every block resident).  `phases` selects
 // steps (1) switching + assembly, (2) colouring, (3) sweeps.  The switching part
-// starts by clearing the degree and cursor arrays and the per-chain counters of the
+// starts by clearing the partner-count array and the per-chain counters of the
 // graph; a launch without it checks that the words left by the earlier launches say
 // a complete graph (and colouring) is there.
 template <uint32_t phases, int model>
@@ -2892,7 +2924,8 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     if (s_halt != 0) return false;
   }
   if constexpr ((phases & PH_SWITCH) != 0) {
-    // the degree and cursor arrays start from zero whatever an earlier launch left
+    // the partner counts start from zero whatever an earlier launch left (the owner
+    // counts are written for every site by the switching)
     if (lead) {
       a.sync->graph_valid = 0;
       a.sync->color_valid = 0;
@@ -2903,17 +2936,14 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
       a.st[c].n_edges = 0;
       for (int p = 0; p < SCO_MAXLEVEL; ++p) a.st[c].kw_rounds[p] = 0;
     }
-    for (int64_t g = gtid(); g < a.G; g += stride) {
-      a.deg[g] = 0;
-      a.fill[g] = 0;
-    }
+    for (int64_t g = gtid(); g < a.G; g += stride) a.deg[g] = 0;
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 1);
     phase_switch<heis>(a, step, lds.list);
     mark(a.trace, 2);
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 3);
-    if (!scan_two_pass(a.deg, a.G, a.row_ptr, a.scan_agg, lds.list, a.sync))
+    if (!scan_two_pass(a.deg, a.own, a.G, a.row_ptr, a.scan_agg, lds.list, a.sync))
       return false;
     if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 4);
@@ -2972,7 +3002,7 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
 
 // Persistent kernel (cooperative launch: every block resident), one step of every
 // chain.  `phases` selects steps (1) switching + assembly, (2) colouring, (3) sweeps.
-// The switching part starts by clearing the degree and cursor arrays and the
+// The switching part starts by clearing the partner-count array and the
 // per-chain counters of the graph; a launch without it checks that the words left by
 // the earlier launches say a complete graph (and colouring) is there.  (Looping over
 // several steps inside one launch was measured to push the fused kernel past its
