@@ -1123,7 +1123,9 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
 // into agg[t]; (2) a device-wide barrier; (3) each block adds the sums of the tiles
 // before each of its tiles and scans the tile.  Global memory is read and written in
 // coalesced rows (item k * kBlock + thread); the scan order goes through LDS, padded
-// one word in 32 against bank conflicts.  out[n] = total.  out may alias in.
+// one word in 32 against bank conflicts.  When no block has more than one tile, a
+// thread keeps its values in registers from (1) to (3) instead of reading them twice.
+// out[n] = total.  out may alias in.
 constexpr int kItems = SCO_SCAN_ITEMS;  // one tile per block at L = 2304 on 256 blocks
 constexpr int kTile = kBlock * kItems;
 constexpr int kScanLds = kTile + kTile / 32;  // words of the padded tile in LDS
@@ -1141,13 +1143,19 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, const uint16_t*
   const int rowb = tid + (tid >> 5), cb = tid * kItems;
   constexpr int kRow = kBlock + kBlock / 32;
   auto pad = [](int x) { return x + (x >> 5); };
+  const bool one = nt <= static_cast<int>(gridDim.x);
+  int32_t kept[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) kept[k] = 0;
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const int tb = t * kTile + tid;
     long long s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const int idx = tb + k * kBlock;
-      s += idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0;
+      const int32_t v = idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0;
+      kept[k] = v;
+      s += v;
     }
     s = block_sum(s);
     if (threadIdx.x == 0) agg[t] = s;
@@ -1159,7 +1167,7 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, const uint16_t*
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const int idx = tb + k * kBlock;
-      lds[rowb + k * kRow] = idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0;
+      lds[rowb + k * kRow] = one ? kept[k] : (idx < n ? in[idx] + static_cast<int32_t>(in2[idx]) : 0);
     }
     // sum of the tiles before t
     long long pre = 0;
@@ -1254,8 +1262,10 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
 // offsets (kScanRow chunks per iteration): an empty row, the usual case, has its
 // lattice neighbour count as union degree, and the sites with bonds are queued; a
 // second pass reads, sorts and checks the queued rows.  Otherwise each site takes the
-// full path, kScan chunks per iteration.  The per-chain maximum and sum gather in LDS
-// (one atomic per wave when the wave is one chain) and reach the chain states once
+// full path, kScan chunks per iteration.  When the block's range is one chain (the
+// usual case) its descriptor is block-uniform and the maxima and sum are kept per
+// thread and reduced once at the end; otherwise they gather in LDS per row (one atomic
+// per wave when the wave is one chain).  Either way they reach the chain states once
 // per block.
 constexpr int kScanRow = 8;
 __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q, int q_cap) {
@@ -1268,6 +1278,24 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) rmax[c] = rsum[c] = rbmx[c] = 0;
   if (threadIdx.x == 0) s_nq = 0;
   __syncthreads();
+  const int c_uni = ch0 < ch1 && a.chunk_chain[ch0] == a.chunk_chain[ch1 - 1] ? a.chunk_chain[ch0] : -1;
+  // per-thread maximum union degree, maximum and sum of bond degrees (c_uni >= 0)
+  int t_umax = 0, t_bmax = 0, t_bsum = 0;
+  auto tally_row = [&](int c, int udeg, int rowlen, bool bonds) __attribute__((always_inline)) {
+    if (c_uni >= 0) {
+      if (c >= 0) {
+        t_umax = max(t_umax, udeg);
+        t_bmax = max(t_bmax, rowlen);
+        t_bsum += rowlen;
+      }
+    } else {
+      wave_max_to(rmax, c, udeg);
+      if (bonds) {
+        wave_max_to(rbmx, c, rowlen);
+        wave_sum_to(rsum, c, rowlen);
+      }
+    }
+  };
   // the full path for up to kScan sites per thread (g < 0: none): row read in one
   // round, sorted in registers when short (nearly all), union degree against the
   // lattice neighbours
@@ -1280,7 +1308,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
       cs[r] = -1;
       r0[r] = r1[r] = 0;
       if (gs[r] >= 0) {
-        cs[r] = a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
+        cs[r] = c_uni >= 0 ? c_uni : a.chunk_chain[gs[r] >> SCO_CHUNK_SHIFT];
         ok[r] = static_cast<int>(gs[r] - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
         if (ok[r]) {
           r0[r] = a.row_ptr[gs[r]];
@@ -1366,10 +1394,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
           for (int t = 0; t < 4; ++t) udeg += (nb[t] >= 0 && !dup[t]) ? 1 : 0;
         }
       }
-      const int c = ok[r] ? cs[r] : -1;
-      wave_max_to(rmax, c, udeg);
-      wave_max_to(rbmx, c, rowlen);
-      wave_sum_to(rsum, c, rowlen);
+      tally_row(ok[r] ? cs[r] : -1, udeg, rowlen, true);
     }
   };
   const bool queued = static_cast<int64_t>(ch1 - ch0) * kBlock <= q_cap;
@@ -1385,7 +1410,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
         cs[r] = -1;
         r0[r] = r1[r] = 0;
         if (ch < ch1) {
-          cs[r] = a.chunk_chain[ch];
+          cs[r] = c_uni >= 0 ? c_uni : a.chunk_chain[ch];
           const int64_t g = (static_cast<int64_t>(ch) << SCO_CHUNK_SHIFT) + threadIdx.x;
           ok[r] = static_cast<int>(g - a.cd[cs[r]].vbase) < a.cd[cs[r]].N;
           if (ok[r]) {
@@ -1419,7 +1444,7 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
             udeg = (x + 1 < d.L) + (x > 0) + (y + 1 < d.L) + (y > 0);
           }
         }
-        wave_max_to(rmax, ok[r] && !push ? cs[r] : -1, udeg);
+        tally_row(ok[r] && !push ? cs[r] : -1, udeg, 0, false);
       }
     }
     __syncthreads();
@@ -1441,6 +1466,11 @@ __device__ __forceinline__ void phase_rowsort(const StepArgs& a, int32_t* lds_q,
         gs[r] = chb + r < ch1 ? (static_cast<int64_t>(chb + r) << SCO_CHUNK_SHIFT) + threadIdx.x : -1;
       full_rows(gs);
     }
+  }
+  if (c_uni >= 0) {
+    wave_max_to(rmax, c_uni, t_umax);
+    wave_max_to(rbmx, c_uni, t_bmax);
+    wave_sum_to(rsum, c_uni, t_bsum);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < a.n_chains; c += kBlock) {
