@@ -99,20 +99,24 @@ struct StepArgs {
   const int32_t* chunk_chain;
   int8_t* spin;
   double* spin3;          // [3 G] Heisenberg spins (x, y, z per site), nullptr for Ising
-  int32_t* deg;           // [G] survivors with the site as partner (cleared by the switching phase)
+  int32_t* deg;           // [G] survivors with the site as partner whose owner's block does
+                          // not hold the site (cleared by the switching phase)
   int32_t* row_ptr;       // [G + 1]
   int32_t* fill;          // [G] the whole-graph colour reduction's dependence counts
-  uint16_t* own;          // [G] survivors with the site as owner (every site written by the
-                          // switching; aliases fill, which the colouring alone uses)
+  uint16_t* own;          // [G] survivors with the site as owner, plus those with the site as
+                          // partner whose owner's block holds the site (every site written
+                          // by the switching; aliases fill, which the colouring alone uses)
   int32_t *ea, *eb, *em;  // survivors: owner, partner (global sites), displacement index
-  int32_t* er;            // survivor's rank among its owner's survivors | its slot among
-                          // its partner's incoming survivors << 16 (as uint32_t)
+  int32_t* er;            // survivor's rank among its owner's survivors | its place in its
+                          // partner's row << 16 (from the front when the owner's block holds
+                          // the partner, else from the back) | that case << 31 (as uint32_t)
   int32_t* col;           // [2 * cap] neighbour (global site)
   int32_t* attr;          // [2 * cap] displacement index
   uint16_t* color;        // [G]
   uint32_t* kw_word;      // [G] colouring state: level:5 | round:9 | colour:9
   int4* rec;              // [G] per-block bucket lists: {site, row start, row end, chain}
-  uint32_t* ecount;       // [nchunks] survivors found in each chunk (own region of cap/nchunks)
+  uint32_t* ecount;       // [nchunks] survivors of the block whose range starts at the chunk,
+                          // stored from that chunk's region on (0 for the block's other chunks)
   long long* scan_agg;    // per-tile sums of the degree scan
   unsigned long long* trace;    // [SCO_TRACE_SLOTS] phase marks of block 0
   int64_t G;

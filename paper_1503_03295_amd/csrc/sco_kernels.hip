@@ -880,6 +880,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     uint32_t np = 0, s1 = total;
     if (phase == 1) {
       __syncthreads();
+      mark(a.trace, 503);
       np = min(s_park, park_cap);
       if (np == 0) break;  // block-uniform
     } else {
@@ -911,6 +912,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         }
       }
       __syncthreads();
+      if (s0 == 0) mark(a.trace, 502);
     }
     const uint32_t nlist = s_nlist;
     bool pool = true;
@@ -1074,6 +1076,7 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
       if (KL > 0)
         for (int b = threadIdx.x; b <= kSwGuide; b += kBlock) lg[b] = ld_global(&d0.guide[b * gs]);
       __syncthreads();
+      mark(a.trace, 501);
       const SwitchTables tb{lC, lhd, lg, KL, d0.guide_inv / gs, d0.K - 1};
       uint16_t* lst = reinterpret_cast<uint16_t*>(lg + kSwGuide + 1);
       run([&](int) -> const ChainDesc& { return d0; }, tb, c_lo, lst, kSwListCap);
@@ -1084,11 +1087,25 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
     }
   }
   __syncthreads();
-  // the partners' counts, from the block's survivor list (issued after the draws, so
-  // no load of the draw loop waits behind them): the count before a survivor's
+  mark(a.trace, 504);
+  // The partners' counts, from the block's survivor list (issued after the draws, so
+  // no load of the draw loop waits behind them).  The count before a survivor's
   // increment is its slot among its partner's incoming survivors, kept beside its rank
+  // (er: rank | place << 16 | in-range bit << 31).  A partner inside the block's own
+  // range (most: the bonds are short) is counted in LDS, then added to its owner
+  // count; one outside it, with a device atomic on deg.  A row holds the owner's
+  // survivors first, by rank, then the in-range incoming ones (place: the owner count
+  // plus the slot), and the others from the row's end (place: the slot).
   const uint32_t ne = min(s_count, cap_blk);
   uint32_t* const er = reinterpret_cast<uint32_t*>(a.er) + e_base;
+  const int64_t glo = static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT;
+  const uint32_t nloc = static_cast<uint32_t>(ch1 - ch0) << SCO_CHUNK_SHIFT;
+  const bool local = nloc / 2u <= static_cast<uint32_t>(kListCap);  // block-uniform
+  uint32_t* const lcnt = reinterpret_cast<uint32_t*>(lds_raw);       // two u16 counts per word
+  if (local) {
+    for (uint32_t k = threadIdx.x; k < nloc / 2u; k += kBlock) lcnt[k] = 0u;
+    __syncthreads();
+  }
   for (uint32_t e0 = 0; e0 < ne; e0 += kScan * kBlock) {
     int32_t pj[kScan];
     uint32_t rk[kScan];
@@ -1102,20 +1119,49 @@ __device__ __forceinline__ void phase_switch(const StepArgs& a, uint32_t step, i
         rk[r] = er[e];
       }
     }
-    int32_t sl[kScan];
+    uint32_t sl[kScan], ow[kScan];
+    bool in[kScan];
 #pragma unroll
-    for (int r = 0; r < kScan; ++r) sl[r] = pj[r] >= 0 ? atomicAdd(&a.deg[pj[r]], 1) : 0;
+    for (int r = 0; r < kScan; ++r) {
+      const uint32_t li = static_cast<uint32_t>(pj[r] - glo);
+      in[r] = local && pj[r] >= 0 && li < nloc;
+      sl[r] = ow[r] = 0u;
+      if (in[r]) {
+        ow[r] = a.own[pj[r]];  // written by this block's owners
+        const uint32_t sh = 16u * (li & 1u);
+        sl[r] = (atomicAdd(&lcnt[li >> 1], 1u << sh) >> sh) & 0xFFFFu;
+      } else if (pj[r] >= 0) {
+        sl[r] = static_cast<uint32_t>(atomicAdd(&a.deg[pj[r]], 1));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kScan; ++r) sl[r] += ow[r];
 #pragma unroll
     for (int r = 0; r < kScan; ++r) {
       const uint32_t e = e0 + r * kBlock + threadIdx.x;
       if (pj[r] < 0) continue;
-      if (sl[r] > 0xFFFF || rk[r] > 0xFFFFu) set_flag(a.sync, SCO_FLAG_OVERFLOW);
-      er[e] = (rk[r] & 0xFFFFu) | (static_cast<uint32_t>(sl[r]) << 16);
+      // an in-range count reaching 2^16 carries into its neighbour: flagged either way
+      if (sl[r] >= 0x7FFFu || rk[r] > 0xFFFFu) set_flag(a.sync, SCO_FLAG_OVERFLOW);
+      er[e] = (rk[r] & 0xFFFFu) | ((sl[r] & 0x7FFFu) << 16) | (in[r] ? 0x80000000u : 0u);
+    }
+  }
+  if (local) {
+    // the in-range counts join the owner counts (this block alone wrote them)
+    __syncthreads();
+    uint32_t* const own2 = reinterpret_cast<uint32_t*>(a.own + glo);
+    for (uint32_t k = threadIdx.x; k < nloc / 2u; k += kBlock) {
+      const uint32_t c = lcnt[k];
+      if (c == 0u) continue;
+      const uint32_t o = own2[k];
+      const uint32_t lo = (o & 0xFFFFu) + (c & 0xFFFFu), hi = (o >> 16) + (c >> 16);
+      if (lo > 0xFFFFu || hi > 0xFFFFu) set_flag(a.sync, SCO_FLAG_OVERFLOW);
+      own2[k] = (lo & 0xFFFFu) | (hi << 16);
     }
   }
   if (threadIdx.x == 0)
     for (int ch = ch0; ch < ch1; ++ch) a.ecount[ch] = ch == ch0 ? ne : 0u;
   tally.flush(a);  // its block sums also order the block's work before the return
+  mark(a.trace, 505);
 }
 
 // ------------------------------------------------------------------ prefix sum
@@ -1210,7 +1256,10 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
   const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
-  for (int ch = ch0; ch < ch1; ++ch) {
+  // the switching stored the block's survivors from its first chunk's region on (the
+  // same grid runs both), and the count there; one read, not one per chunk
+  if (ch0 < ch1) {
+    const int ch = ch0;
     const uint32_t e0 = static_cast<uint32_t>(ch) * cap_chunk, e1 = e0 + a.ecount[ch];
     // kScan survivors per thread and iteration, their loads issued together
     for (uint32_t eb = e0; eb < e1; eb += kScan * kBlock) {
@@ -1229,15 +1278,17 @@ __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
         }
       }
       // the owner's entries at the front of its row, at their rank; the partner's
-      // incoming entries from the back of its row, at their slot
+      // entry at its place: from the front when its owner's block holds the partner
+      // (after the partner's own entries), else from the back
       int64_t pu[kScan], pw[kScan];
 #pragma unroll
       for (int r = 0; r < kScan; ++r) {
         pu[r] = pw[r] = -1;
         if (ok[r]) {
           const uint32_t rs = static_cast<uint32_t>(rk[r]);
+          const int64_t place = (rs >> 16) & 0x7FFFu;
           pu[r] = static_cast<int64_t>(a.row_ptr[u[r]]) + (rs & 0xFFFFu);
-          pw[r] = static_cast<int64_t>(a.row_ptr[w[r] + 1]) - 1 - (rs >> 16);
+          pw[r] = (rs >> 31) ? a.row_ptr[w[r]] + place : a.row_ptr[w[r] + 1] - 1 - place;
         }
       }
 #pragma unroll
