@@ -2999,8 +2999,10 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     // written only by the last arriver of a barrier, which every block of this launch
     // reaches after this check; a timeout needs seconds of waiting inside a launch.
     __shared__ uint32_t s_halt;
-    if (threadIdx.x == 0)
-      s_halt = (ld_poll(&a.sync->halt) != 0 || (ld_poll(&a.sync->flags) & SCO_FLAG_TIMEOUT) != 0) ? 1u : 0u;
+    if (threadIdx.x == 0) {
+      const uint32_t h = ld_poll(&a.sync->halt), f = ld_poll(&a.sync->flags);  // both in flight
+      s_halt = (h != 0 || (f & SCO_FLAG_TIMEOUT) != 0) ? 1u : 0u;
+    }
     __syncthreads();
     if (s_halt != 0) return false;
   }
