@@ -113,6 +113,18 @@ def test_ragged_batch_of_chains():
     run_parity(params, 30, graph_every=3, obs_every=10)
 
 
+def test_smallest_lattices():
+    """The smallest lattices the boundary accepts, in one batch: an open 2 x 2 and
+    3 x 3 (a handful of bonds, a palette larger than the lattice) and periodic 4 x 4
+    and 6 x 6 (the image sum and the self-conjugate displacements at their smallest)."""
+    params = [workloads.chain(2, False, 1.0, 1.0, chain_id=0, n_sw=2),
+              workloads.chain(3, False, 0.7, 2.0, chain_id=1),
+              workloads.chain(4, True, 1.5, 1.0, chain_id=2, n_sw=3),
+              workloads.chain(6, True, 0.9, 2.0, chain_id=3)]
+    log("smallest lattices")
+    run_parity(params, 40, graph_every=1, obs_every=5)
+
+
 def test_split_entry_points_equal_step():
     """sco_switch + sco_color + sco_sweep == sco_step."""
     from paper_1503_03295_amd import SCO
