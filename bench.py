@@ -276,7 +276,7 @@ def main() -> int:
     ap.add_argument("--n-sw", type=int, default=1)
     ap.add_argument("--kappa", type=float, default=1.0)
     ap.add_argument("--phase-steps", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nsw100", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
