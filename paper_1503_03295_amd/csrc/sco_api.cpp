@@ -393,6 +393,9 @@ int consume_flags(sco_ctx* c) {
   // the rest of the sync block, the halt word included)
   c->graph_state = 0;
   HIP_TRY(hipMemsetAsync(at<SyncWords>(c, c->lay.off_sync), 0, sizeof(SyncWords), c->stream));
+  // the partner counts start every switching at zero; a stopped step may have left
+  // them anywhere (the scatter clears them only in a step that reached it)
+  HIP_TRY(hipMemsetAsync(at<int32_t>(c, c->lay.off_deg), 0, sizeof(int32_t) * c->lay.G, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (f & SCO_FLAG_TIMEOUT) return SCO_ETIMEOUT;
   if (f & SCO_FLAG_OVERFLOW) return SCO_EOVERFLOW;

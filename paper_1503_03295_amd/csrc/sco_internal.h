@@ -100,7 +100,8 @@ struct StepArgs {
   int8_t* spin;
   double* spin3;          // [3 G] Heisenberg spins (x, y, z per site), nullptr for Ising
   int32_t* deg;           // [G] survivors with the site as partner whose owner's block does
-                          // not hold the site (cleared by the switching phase)
+                          // not hold the site (zero at every switching: cleared by the
+                          // scatter for the next step, by the host at set-up and after a flag)
   int32_t* row_ptr;       // [G + 1]
   int32_t* fill;          // [G] the whole-graph colour reduction's dependence counts
   uint16_t* own;          // [G] survivors with the site as owner, plus those with the site as

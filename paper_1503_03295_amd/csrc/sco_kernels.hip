@@ -1250,12 +1250,17 @@ __device__ __forceinline__ bool scan_two_pass(const int32_t* in, const uint16_t*
   return true;
 }
 
-// both directions of every survivor into the CSR
+// both directions of every survivor into the CSR; the partner counts of the block's
+// chunks back to zero for the next step's switching (the scan has read them, and
+// nothing later in the step does)
 __device__ __forceinline__ void phase_scatter(const StepArgs& a) {
   const uint32_t cap_chunk = a.cap_und / static_cast<uint32_t>(a.nchunks);
   const int cpb = (a.nchunks + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
   const int ch0 = min(static_cast<int>(blockIdx.x) * cpb, a.nchunks), ch1 = min(ch0 + cpb, a.nchunks);
   const int64_t cap2 = 2 * static_cast<int64_t>(a.cap_und);
+  for (int64_t g = (static_cast<int64_t>(ch0) << SCO_CHUNK_SHIFT) + threadIdx.x;
+       g < (static_cast<int64_t>(ch1) << SCO_CHUNK_SHIFT); g += kBlock)
+    a.deg[g] = 0;
   // the switching stored the block's survivors from its first chunk's region on (the
   // same grid runs both), and the count there; one read, not one per chunk
   if (ch0 < ch1) {
@@ -2985,9 +2990,9 @@ __device__ __forceinline__ bool phase_sweep_heis(const StepArgs& a, uint32_t ste
 // ------------------------------------------------------------------ the step
 // Persistent kernel (cooperative launch: every block resident).  `phases` selects
 // steps (1) switching + assembly, (2) colouring, (3) sweeps.  The switching part
-// starts by clearing the partner-count array and the per-chain counters of the
-// graph; a launch without it checks that the words left by the earlier launches say
-// a complete graph (and colouring) is there.
+// starts by clearing the per-chain counters of the graph; a launch without it checks
+// that the words left by the earlier launches say a complete graph (and colouring) is
+// there.
 template <uint32_t phases, int model>
 __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, PhaseLds& lds, KwShared& ks) {
   constexpr bool heis = model == SCO_MODEL_HEIS;
@@ -3007,8 +3012,11 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
     if (s_halt != 0) return false;
   }
   if constexpr ((phases & PH_SWITCH) != 0) {
-    // the partner counts start from zero whatever an earlier launch left (the owner
-    // counts are written for every site by the switching)
+    // The partner counts are zero here: the scatter of the step before cleared them
+    // once the scan had read them (the host clears them at set-up and after a step
+    // that raised a flag, which may have stopped anywhere); the owner counts are
+    // written for every site by the switching.  The graph counters of the chain
+    // states are next written by the row sort, four device barriers on.
     if (lead) {
       a.sync->graph_valid = 0;
       a.sync->color_valid = 0;
@@ -3019,8 +3027,6 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
       a.st[c].n_edges = 0;
       for (int p = 0; p < SCO_MAXLEVEL; ++p) a.st[c].kw_rounds[p] = 0;
     }
-    for (int64_t g = gtid(); g < a.G; g += stride) a.deg[g] = 0;
-    if (!grid_barrier(a.sync)) return false;
     mark(a.trace, 1);
     phase_switch<heis>(a, step, lds.list);
     mark(a.trace, 2);
@@ -3085,9 +3091,9 @@ __device__ __forceinline__ bool step_body(const StepArgs& a, uint32_t step, Phas
 
 // Persistent kernel (cooperative launch: every block resident), one step of every
 // chain.  `phases` selects steps (1) switching + assembly, (2) colouring, (3) sweeps.
-// The switching part starts by clearing the partner-count array and the
-// per-chain counters of the graph; a launch without it checks that the words left by
-// the earlier launches say a complete graph (and colouring) is there.  (Looping over
+// The switching part starts by clearing the per-chain counters of the graph; a
+// launch without it checks that the words left by the earlier launches say a complete
+// graph (and colouring) is there.  (Looping over
 // several steps inside one launch was measured to push the fused kernel past its
 // register budget into spills, for a saving of a few microseconds per step.)
 template <uint32_t phases, int model>
