@@ -1644,8 +1644,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
   uint16_t* const t_brank = tl.brank;
   uint16_t* const t_boff = tl.boff;
   uint16_t* const t_adj = tl.adj;
-  __shared__ int32_t t_off[SCO_MAXQ + 1];
-  __shared__ int32_t t_fill[SCO_MAXQ];
+  __shared__ int32_t t_off[SCO_MAXQ + 1];  // class offsets of the level's list
+  __shared__ int32_t t_cnt[SCO_MAXQ + 1];  // class c counted at c + 1; zero between levels
+  __shared__ int32_t t_fill[SCO_MAXQ];     // zero between levels
   __shared__ int32_t t_wsum[kWaves];
   __shared__ int32_t t_rounds, t_nbonded;
   const uint32_t lane = lane_id();
@@ -1782,6 +1783,9 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
     }
     // level 0: colour i mod q (cr held the partner counts until here)
     for (int i = tid; i < n; i += kBlock) t_cr[i] = static_cast<uint16_t>(i - div16(i, mq) * q);
+    for (int k = tid; k <= q; k += kBlock) t_cnt[k] = 0;
+    for (int k = tid; k < q; k += kBlock) t_fill[k] = 0;
+    if (tid == 0) t_rounds = 0;
     __syncthreads();
     if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 30);
     for (int p = 1; p <= P; ++p) {
@@ -1789,20 +1793,20 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       const int H = q << (p - 1);
       const uint32_t mH = magic16(static_cast<uint32_t>(H));
       const int npend = static_cast<int>(pending_count(n, H));
-      for (int k = threadIdx.x; k <= q; k += kBlock) t_off[k] = 0;
-      if (threadIdx.x == 0) t_rounds = 0;
-      __syncthreads();
+      // t_cnt, t_fill and t_rounds are zero here (cleared before the barrier that ends
+      // the level before)
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
-        atomicAdd(&t_off[(t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF) + 1], 1);
+        atomicAdd(&t_cnt[(t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF) + 1], 1);
       }
       __syncthreads();
-      if (wave == 0) {  // exclusive prefix of the q <= 255 counts, four per lane
+      {  // every wave takes the exclusive prefix of the q <= 255 counts (four per lane)
+         // and writes the same offsets, so no wave waits for another before bucketing
         int cnt[4], s = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int idx = 1 + 4 * static_cast<int>(lane) + r;
-          cnt[r] = idx <= q ? t_off[idx] : 0;
+          cnt[r] = idx <= q ? t_cnt[idx] : 0;
           s += cnt[r];
         }
         int incl = s;
@@ -1817,9 +1821,8 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
           run += cnt[r];
           if (idx <= q) t_off[idx] = run;
         }
+        if (lane == 0) t_off[0] = 0;
       }
-      for (int k = threadIdx.x; k < q; k += kBlock) t_fill[k] = 0;
-      __syncthreads();
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 60 + p);
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
@@ -1923,10 +1926,18 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       if (q <= 32) run_classes(ColorSet32{});
       else if (q <= 64) run_classes(ColorSet64{});
       else run_classes(ColorSet{});
+      // the counts for the next level start from zero (the last class pass has read
+      // its offsets)
+      for (int k = tid; k <= q; k += kBlock) t_cnt[k] = 0;
+      for (int k = tid; k < q; k += kBlock) t_fill[k] = 0;
       __syncthreads();
-      if (threadIdx.x == 0 && t_rounds > 0) atomicMax(&a.st[c].kw_rounds[p], t_rounds);
-      // Eq. (5): a level takes at most q rounds (or the cap the host set)
-      if (threadIdx.x == 0 && t_rounds > (a.round_cap > 0 ? a.round_cap : q)) set_flag(a.sync, SCO_FLAG_ROUNDS);
+      if (threadIdx.x == 0) {
+        const int rounds = t_rounds;
+        t_rounds = 0;  // written next after the next level's bucketing barrier
+        if (rounds > 0) atomicMax(&a.st[c].kw_rounds[p], rounds);
+        // Eq. (5): a level takes at most q rounds (or the cap the host set)
+        if (rounds > (a.round_cap > 0 ? a.round_cap : q)) set_flag(a.sync, SCO_FLAG_ROUNDS);
+      }
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 40 + p);
     }
     const uint32_t tag = static_cast<uint32_t>(P) << 18;
