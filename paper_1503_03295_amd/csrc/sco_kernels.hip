@@ -422,6 +422,33 @@ __device__ __forceinline__ void wave_sum_to(int* per_chain, int c, int val) {
   }
 }
 
+// Exclusive offsets of the q <= 255 class counts cnt[1..q] into off[0..q], taken by
+// one wave (four counts per lane).  Every wave of a block may run it: they write the
+// same values, so each can use the offsets at once, with no barrier after it.
+__device__ __forceinline__ void wave_class_offsets(const int32_t* cnt, int32_t* off, int q) {
+  const int lane = static_cast<int>(lane_id());
+  int c4[4], s = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int idx = 1 + 4 * lane + r;
+    c4[r] = idx <= q ? cnt[idx] : 0;
+    s += c4[r];
+  }
+  int incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int x = __shfl_up(incl, o);
+    if (lane >= o) incl += x;
+  }
+  int run = incl - s;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int idx = 1 + 4 * lane + r;
+    run += c4[r];
+    if (idx <= q) off[idx] = run;
+  }
+  if (lane == 0) off[0] = 0;
+}
+
 // 256-bit colour set without dynamic register indexing
 struct ColorSet {
   uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
@@ -1800,29 +1827,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
         atomicAdd(&t_cnt[(t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF) + 1], 1);
       }
       __syncthreads();
-      {  // every wave takes the exclusive prefix of the q <= 255 counts (four per lane)
-         // and writes the same offsets, so no wave waits for another before bucketing
-        int cnt[4], s = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int idx = 1 + 4 * static_cast<int>(lane) + r;
-          cnt[r] = idx <= q ? t_cnt[idx] : 0;
-          s += cnt[r];
-        }
-        int incl = s;
-        for (int o = 1; o < 64; o <<= 1) {
-          const int x = __shfl_up(incl, o);
-          if (lane >= static_cast<uint32_t>(o)) incl += x;
-        }
-        int run = incl - s;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int idx = 1 + 4 * static_cast<int>(lane) + r;
-          run += cnt[r];
-          if (idx <= q) t_off[idx] = run;
-        }
-        if (lane == 0) t_off[0] = 0;
-      }
+      wave_class_offsets(t_cnt, t_off, q);  // in every wave: no barrier before bucketing
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 60 + p);
       for (int k = threadIdx.x; k < npend; k += kBlock) {
         const int j = div16(k, mH);
@@ -1965,6 +1970,7 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
 // before it is used as an index.
 __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShared& ks, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
+  __shared__ int32_t bcnt[SCO_MAXQ + 1];  // class c counted at c + 1
   __shared__ int32_t bfill[SCO_MAXQ];
   __shared__ int32_t brounds[SCO_MAXCHAINS];
   __shared__ long long cpre[SCO_MAXCHAINS + 1];
@@ -1995,7 +2001,8 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
       for (int w = 0; w < wave; ++w) off += wtot[w];
       if (c < nch) cpre[c] = off + incl - np;
       if (c == nch - 1) cpre[nch] = off + incl;
-      for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
+      for (int k = tid; k <= qmax; k += kBlock) bcnt[k] = 0;
+      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
       for (int k = tid; k < nch; k += kBlock) brounds[k] = 0;
       if (tid == 0) s_pos = 0;
       __syncthreads();
@@ -2053,17 +2060,12 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
               set_flag(a.sync, SCO_FLAG_PALETTE);
               continue;
             }
-            if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+            if (pass == 0) atomicAdd(&bcnt[cc + 1], 1);
             else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(kb + r * kBlock + tid - k0);
           }
         }
         __syncthreads();
-        if (pass == 0) {
-          if (threadIdx.x == 0)
-            for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-          for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
-          __syncthreads();
-        }
+        if (pass == 0) wave_class_offsets(bcnt, boff, qmax);  // in every wave
       }
     };
     // a share of at most kHeldKW sites per thread: every colour loaded at once and kept
@@ -2090,13 +2092,10 @@ __device__ __forceinline__ bool phase_kw_global(const StepArgs& a, const KwShare
           wd[r] = ~0u;
           continue;
         }
-        atomicAdd(&boff[cc + 1], 1);
+        atomicAdd(&bcnt[cc + 1], 1);
       }
       __syncthreads();
-      if (threadIdx.x == 0)
-        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
-      __syncthreads();
+      wave_class_offsets(bcnt, boff, qmax);  // in every wave: no barrier before the scatter
 #pragma unroll
       for (int r = 0; r < kHeldKW; ++r)
         if (wd[r] != ~0u) lst[boff[wd[r]] + atomicAdd(&bfill[wd[r]], 1)] = r * kBlock + tid;
@@ -2424,6 +2423,7 @@ constexpr int kLocalChains = 4;  // chain descriptors of a block's range held in
 
 __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, int32_t* lds_list) {
   __shared__ int32_t boff[SCO_MAXQ + 1];
+  __shared__ int32_t bcnt[SCO_MAXQ + 1];  // class c counted at c + 1
   __shared__ int32_t bfill[SCO_MAXQ];
   // accepted flips of the block per chain: up -> down in the low 32 bits, down -> up in
   // the high 32 bits (the magnetisation moves by 2 (high - low))
@@ -2465,7 +2465,8 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
   const bool flush_each_sweep = static_cast<int64_t>(a.nsw_max) * (r1 - r0) >= (1ll << 31);
   if (local_cd)
     for (int i = tid; i <= c_hi - c_lo; i += kBlock) lcd[i] = a.cd[c_lo + i];
-  for (int k = tid; k <= qmax; k += kBlock) boff[k] = 0;
+  for (int k = tid; k <= qmax; k += kBlock) bcnt[k] = 0;
+  for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
   for (int c = tid; c < a.n_chains; c += kBlock) bacc[c] = 0;
   __syncthreads();
   // The list in LDS and the chain descriptors in LDS (the usual case), or both in
@@ -2499,13 +2500,10 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
           col[r] = -1;
           continue;
         }
-        atomicAdd(&boff[col[r] + 1], 1);
+        atomicAdd(&bcnt[col[r] + 1], 1);
       }
       __syncthreads();
-      if (threadIdx.x == 0)
-        for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-      for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
-      __syncthreads();
+      wave_class_offsets(bcnt, boff, qmax);  // in every wave: no barrier before the scatter
 #pragma unroll
       for (int r = 0; r < kHeldSw; ++r)
         if (col[r] >= 0) lst[boff[col[r]] + atomicAdd(&bfill[col[r]], 1)] = r * kBlock + tid;
@@ -2535,17 +2533,12 @@ __device__ __forceinline__ bool phase_sweep(const StepArgs& a, uint32_t step, in
             if (pass == 0) set_flag(a.sync, SCO_FLAG_PALETTE);
             continue;
           }
-          if (pass == 0) atomicAdd(&boff[cc + 1], 1);
+          if (pass == 0) atomicAdd(&bcnt[cc + 1], 1);
           else lst[boff[cc] + atomicAdd(&bfill[cc], 1)] = static_cast<int32_t>(gb + r * kBlock + tid - r0);
         }
       }
       __syncthreads();
-      if (pass == 0) {
-        if (threadIdx.x == 0)
-          for (int k = 0; k < qmax; ++k) boff[k + 1] += boff[k];
-        for (int k = tid; k < qmax; k += kBlock) bfill[k] = 0;
-        __syncthreads();
-      }
+      if (pass == 0) wave_class_offsets(bcnt, boff, qmax);  // in every wave
     }
     mark(a.trace, 22);
 
