@@ -191,8 +191,9 @@ int sco_run_noalloc(const sco_chain_params* params, int n_chains, const int8_t* 
                     int8_t* dev_spins_out, uint64_t first_step, int n_steps, sco_obs* host_obs,
                     void* stream);
 
-/* sco_run as one replay of a HIP graph: n_steps cooperative launches of the step
- * kernel, each node depending on the one before.  The graph is built on the first call
+/* sco_run as one replay of a HIP graph: the steps' cooperative kernel launches (three
+ * per step in the default step form, one in the fused form), each node depending on
+ * the one before.  The graph is built on the first call
  * with this n_steps (and schedule) and kept in the context; later calls rewrite the
  * nodes' step indices and replay it.  The graph holds kernel nodes only.  Same results
  * as sco_run; synchronises and reports the steps' flags. */
