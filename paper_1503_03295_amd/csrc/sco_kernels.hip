@@ -2917,11 +2917,14 @@ __device__ __forceinline__ bool phase_sweep_heis(const StepArgs& a, uint32_t ste
       __syncthreads();
     }
   }
+  // the sweeps, in two inlined copies: the block's range in one chain (the usual case;
+  // its descriptor block-uniform, read with scalar loads) or in several
+  auto sweeps = [&](const auto& chain_of) __attribute__((always_inline)) -> bool {
   for (int s = 0; s < a.nsw_max; ++s) {
     for (int cc = 0; cc < qmax; ++cc) {
       for (int k = hoff[cc] + tid; k < hoff[cc + 1]; k += kBlock) {
         const int64_t g = r0 + lst[k];
-        const int c = a.chunk_chain[g >> SCO_CHUNK_SHIFT];
+        const int c = chain_of(g);
         const ChainDesc& d = a.cd[c];
         const int nsw = a.nsw_override >= 0 ? a.nsw_override : d.n_sw;
         if (s >= nsw) continue;
@@ -2980,6 +2983,13 @@ __device__ __forceinline__ bool phase_sweep_heis(const StepArgs& a, uint32_t ste
       if (!grid_barrier(a.sync)) return false;
     }
   }
+  return true;
+  };
+  const int c_lo = r0 < r1 ? a.chunk_chain[r0 >> SCO_CHUNK_SHIFT] : 0;
+  const int c_hi = r0 < r1 ? a.chunk_chain[(r1 - 1) >> SCO_CHUNK_SHIFT] : 0;
+  const bool ok = c_lo == c_hi ? sweeps([&](int64_t) { return c_lo; })
+                               : sweeps([&](int64_t g) { return a.chunk_chain[g >> SCO_CHUNK_SHIFT]; });
+  if (!ok) return false;
   tally.flush(a);
   const unsigned long long ta = block_sum(static_cast<unsigned long long>(acc0));
   if (tid == 0 && ta && tally.c0 < a.n_chains) atomicAdd(&a.st[tally.c0].accepted, ta);
