@@ -1822,19 +1822,50 @@ __device__ __forceinline__ void phase_kw_local(const StepArgs& a, const KwShared
       const int npend = static_cast<int>(pending_count(n, H));
       // t_cnt, t_fill and t_rounds are zero here (cleared before the barrier that ends
       // the level before)
-      for (int k = threadIdx.x; k < npend; k += kBlock) {
-        const int j = div16(k, mH);
-        atomicAdd(&t_cnt[(t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF) + 1], 1);
+      // classes 0 and 1 (most pending sites) are counted per wave by ballot, the others
+      // with one LDS atomic per site
+      for (int kb = 0; kb < npend; kb += kBlock) {
+        const int k = kb + tid;
+        int cc = -1;
+        if (k < npend) {
+          const int j = div16(k, mH);
+          cc = t_cr[(2 * j + 1) * H + (k - j * H)] & 0xFF;
+        }
+        const uint64_t m0 = __ballot(cc == 0), m1 = __ballot(cc == 1);
+        if (lane == 0) {
+          if (m0) atomicAdd(&t_cnt[1], __popcll(m0));
+          if (m1) atomicAdd(&t_cnt[2], __popcll(m1));
+        }
+        if (cc >= 2) atomicAdd(&t_cnt[cc + 1], 1);
       }
       __syncthreads();
       wave_class_offsets(t_cnt, t_off, q);  // in every wave: no barrier before bucketing
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 60 + p);
-      for (int k = threadIdx.x; k < npend; k += kBlock) {
-        const int j = div16(k, mH);
-        const int i = (2 * j + 1) * H + (k - j * H);
-        const int cc = t_cr[i] & 0xFF;
-        t_list[t_off[cc] + atomicAdd(&t_fill[cc], 1)] = static_cast<uint16_t>(i);
-        t_cr[i] = static_cast<uint16_t>(cc);  // undecided at this level
+      for (int kb = 0; kb < npend; kb += kBlock) {
+        const int k = kb + tid;
+        int cc = -1, i = 0;
+        if (k < npend) {
+          const int j = div16(k, mH);
+          i = (2 * j + 1) * H + (k - j * H);
+          cc = t_cr[i] & 0xFF;
+        }
+        // classes 0 and 1: one LDS atomic per wave, the lanes ranked by ballot
+        const uint64_t m0 = __ballot(cc == 0), m1 = __ballot(cc == 1);
+        int b0 = 0, b1 = 0;
+        if (lane == 0) {
+          if (m0) b0 = atomicAdd(&t_fill[0], __popcll(m0));
+          if (m1) b1 = atomicAdd(&t_fill[1], __popcll(m1));
+        }
+        b0 = __shfl(b0, 0);
+        b1 = __shfl(b1, 0);
+        if (cc >= 0) {
+          const uint64_t below = (1ull << lane) - 1ull;
+          const int slot = cc == 0   ? t_off[0] + b0 + __popcll(m0 & below)
+                           : cc == 1 ? t_off[1] + b1 + __popcll(m1 & below)
+                                     : t_off[cc] + atomicAdd(&t_fill[cc], 1);
+          t_list[slot] = static_cast<uint16_t>(i);
+          t_cr[i] = static_cast<uint16_t>(cc);  // undecided at this level
+        }
       }
       __syncthreads();
       if (tile == static_cast<int>(blockIdx.x)) mark(a.trace, 80 + p);
